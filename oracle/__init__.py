@@ -1,0 +1,286 @@
+"""The oracle -- TEST INFRASTRUCTURE, not part of the product.
+
+A plain, slow, complex128 CPU simulator of what the HIP path computes,
+written from the paper's definitions and pinned by the ``-m "not gpu"``
+tests against values the paper prints, closed forms, library routines
+(``numpy.fft``, ``scipy.linalg.expm``) and brute force.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import it; the product package never does.
+
+* ``dq_oracle.c``: gate matrices, the textbook gather/multiply/scatter loop,
+  Pauli-string expectations (letters applied as ordinary gates), marginal
+  probabilities.  Pure-state evolution is the equation of paper section 4.1;
+  expectations and measurement follow the API overview of section 4.2.
+* this module: per-gate angles (``scale * source``), batching over samples,
+  and the two reference gradients -- the parameter-shift rule (exact for
+  gates exp(-i t G/2) whose generator G has eigenvalues +-1, and for the
+  controlled phase, whose generator has eigenvalues 0 and 1) and central
+  finite differences.  The adjoint method that the paper names for its
+  distributed simulator (section 7.2) is *not* re-implemented here: the
+  oracle's gradients come from the definition of the derivative.
+* ``kron.py``: an independent numpy brute-force checker (tensor
+  contraction / Kronecker products) for up to six qubits.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dq_oracle.c")
+_SO = os.path.join(_HERE, "_dq_oracle.so")
+
+OPCODE = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "cnot": 7, "cz": 8,
+          "swap": 9, "cp": 10, "rzz": 11, "unitary": 12}
+# gates whose derivative the two-term shift rule gives exactly
+SHIFT_RULE_GATES = ("rx", "ry", "rz", "rzz", "cp")
+
+_lib = None
+_lock = threading.Lock()
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, no vectorisation tricks)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_SO):
+                build(force=False)
+            L = ctypes.CDLL(_SO)
+            dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+            L.orc_gate_matrix.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+            L.orc_gate_matrix.restype = ctypes.c_int
+            L.orc_apply.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, dp]
+            L.orc_apply.restype = None
+            L.orc_run.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp]
+            L.orc_run.restype = ctypes.c_int
+            L.orc_pauli_expval.argtypes = [ctypes.c_int, dp, ctypes.c_char_p, dp]
+            L.orc_pauli_expval.restype = ctypes.c_double
+            L.orc_prob_zero.argtypes = [ctypes.c_int, dp, ctypes.c_int]
+            L.orc_prob_zero.restype = ctypes.c_double
+            _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+# ------------------------------------------------------------ circuit encoding
+class _Encoded:
+    """The gate list as flat int/double arrays for the C loop."""
+
+    def __init__(self, circuit):
+        G = len(circuit.gates)
+        self.n = circuit.n
+        self.ops = np.array([OPCODE[g.op] for g in circuit.gates], dtype=np.intc)
+        self.nq = np.array([g.nq for g in circuit.gates], dtype=np.intc)
+        self.wires = np.zeros(5 * max(G, 1), dtype=np.intc)
+        for i, g in enumerate(circuit.gates):
+            self.wires[5 * i:5 * i + g.nq] = g.wires
+        dense = [np.ascontiguousarray(g.matrix, dtype=np.complex128).ravel()
+                 for g in circuit.gates if g.op == "unitary"]
+        self.dense = (np.concatenate(dense) if dense else np.zeros(1, np.complex128)).view(np.float64)
+        self.gates = circuit.gates
+
+    def angles(self, params, data, b: int) -> np.ndarray:
+        """theta_g = scale * (params[idx] | data[idx] | 1)."""
+        th = np.zeros(max(len(self.gates), 1))
+        for i, g in enumerate(self.gates):
+            if g.src == "param":
+                p = np.asarray(params, float)
+                th[i] = g.scale * (p[b, g.idx] if p.ndim == 2 else p[g.idx])
+            elif g.src == "data":
+                th[i] = g.scale * float(np.asarray(data, float)[b, g.idx])
+            else:
+                th[i] = g.scale
+        return th
+
+
+def _run_angles(enc: _Encoded, theta: np.ndarray, psi0: Optional[np.ndarray] = None) -> np.ndarray:
+    psi = np.zeros(1 << enc.n, dtype=np.complex128)
+    if psi0 is None:
+        psi[0] = 1.0
+    else:
+        psi[:] = psi0
+    pv = psi.view(np.float64)
+    rc = lib().orc_run(enc.n, _dp(pv), len(enc.gates), _ip(enc.ops), _ip(enc.nq), _ip(enc.wires),
+                       _dp(theta), _dp(enc.dense))
+    if rc != 0:
+        raise ValueError("oracle: unknown gate")
+    return psi
+
+
+# ------------------------------------------------------------ public API
+def gate_matrix(op: str, theta: float = 0.0) -> np.ndarray:
+    buf = np.zeros(32)
+    k = lib().orc_gate_matrix(OPCODE[op], float(theta), _dp(buf))
+    if k < 0:
+        raise ValueError(op)
+    d = 1 << k
+    return buf[:2 * d * d].view(np.complex128).reshape(d, d).copy()
+
+
+def apply_matrix(n: int, psi: np.ndarray, wires: Sequence[int], U: np.ndarray) -> np.ndarray:
+    """Apply a dense matrix to ``wires`` of a copy of ``psi``."""
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    Ui = np.ascontiguousarray(U, dtype=np.complex128)
+    w = np.array(wires, dtype=np.intc)
+    lib().orc_apply(n, _dp(out.view(np.float64)), len(wires), _ip(w), _dp(Ui.view(np.float64)))
+    return out
+
+
+def state(circuit, params=None, data=None, b: int = 0, psi0=None) -> np.ndarray:
+    """Final state of sample ``b`` (complex128, length 2^n)."""
+    enc = _Encoded(circuit)
+    return _run_angles(enc, enc.angles(params, data, b), psi0)
+
+
+def pauli_expval(n: int, psi: np.ndarray, letters: str, check_imag: float = 1e-10) -> float:
+    im = ctypes.c_double(0.0)
+    pv = np.ascontiguousarray(psi, dtype=np.complex128).view(np.float64)
+    re = lib().orc_pauli_expval(n, _dp(pv), letters.encode("ascii"), ctypes.byref(im))
+    if not np.isfinite(re) or abs(im.value) > check_imag * max(1.0, np.vdot(psi, psi).real):
+        raise ValueError("oracle: <P> not real (%r, %r)" % (re, im.value))
+    return re
+
+
+def expvals(n: int, psi: np.ndarray, observables) -> np.ndarray:
+    """E[o] = sum_k c_k <psi|P_k|psi> for each observable o."""
+    out = np.zeros(len(observables))
+    for o, obs in enumerate(observables):
+        out[o] = sum(c * pauli_expval(n, psi, letters) for c, letters in obs)
+    return out
+
+
+def prob_zero(n: int, psi: np.ndarray, wire: int) -> float:
+    pv = np.ascontiguousarray(psi, dtype=np.complex128).view(np.float64)
+    return lib().orc_prob_zero(n, _dp(pv), wire)
+
+
+def _pool(threads: Optional[int]):
+    return ThreadPoolExecutor(max_workers=threads or 1)
+
+
+def forward(circuit, params, data, observables, batch: int, threads: Optional[int] = None,
+            samples: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Expectations E[b, o] for the listed samples (default: all)."""
+    enc = _Encoded(circuit)
+    samples = list(range(batch)) if samples is None else list(samples)
+
+    def one(b):
+        return expvals(circuit.n, _run_angles(enc, enc.angles(params, data, b)), observables)
+
+    with _pool(threads) as ex:
+        rows = list(ex.map(one, samples))
+    return np.array(rows).reshape(len(samples), len(observables))
+
+
+def _source_gates(circuit):
+    return [i for i, g in enumerate(circuit.gates) if g.src in ("param", "data")]
+
+
+def grad_param_shift(circuit, params, data, observables, weights, batch: int,
+                     threads: Optional[int] = None, samples: Optional[Sequence[int]] = None,
+                     gate_subset: Optional[Sequence[int]] = None):
+    """Vector-Jacobian product of L = sum_{b,o} w[b,o] E[b,o] by the two-term
+    parameter-shift rule, applied to every gate occurrence that reads a
+    parameter or a data entry:
+        dE/dtheta_g = (E(theta_g + pi/2) - E(theta_g - pi/2)) / 2,
+    chained through theta_g = scale * source.
+    Returns (grad_params shaped like params, grad_data shaped like data)."""
+    enc = _Encoded(circuit)
+    w = np.asarray(weights, float).reshape(batch, len(observables))
+    p = np.asarray(params, float) if params is not None else np.zeros(0)
+    gp = np.zeros_like(p)
+    gd = None if data is None else np.zeros_like(np.asarray(data, float))
+    samples = list(range(batch)) if samples is None else list(samples)
+    gates = _source_gates(circuit) if gate_subset is None else list(gate_subset)
+    for i in gates:
+        if circuit.gates[i].op not in SHIFT_RULE_GATES:
+            raise ValueError("no shift rule for %s" % circuit.gates[i].op)
+
+    jobs = [(b, i) for b in samples for i in gates]
+
+    def one(job):
+        b, i = job
+        th = enc.angles(params, data, b)
+        out = 0.0
+        for sgn in (+1.0, -1.0):
+            t2 = th.copy()
+            t2[i] += sgn * np.pi / 2
+            e = expvals(circuit.n, _run_angles(enc, t2), observables)
+            out += sgn * float(np.dot(w[b], e)) / 2.0
+        return out
+
+    with _pool(threads) as ex:
+        vals = list(ex.map(one, jobs))
+    for (b, i), v in zip(jobs, vals):
+        g = circuit.gates[i]
+        if g.src == "param":
+            if gp.ndim == 2:
+                gp[b, g.idx] += g.scale * v
+            else:
+                gp[g.idx] += g.scale * v
+        else:
+            gd[b, g.idx] += g.scale * v
+    return gp, gd
+
+
+def grad_fd(circuit, params, data, observables, weights, batch: int, h: float = 1e-6,
+            threads: Optional[int] = None, samples: Optional[Sequence[int]] = None,
+            param_subset: Optional[Sequence[int]] = None, with_data: bool = True):
+    """Central finite differences (L(x+h) - L(x-h)) / 2h of the same VJP, on
+    each parameter (and each data entry)."""
+    w = np.asarray(weights, float).reshape(batch, len(observables))
+    p = np.asarray(params, float) if params is not None else np.zeros(0)
+    samples = list(range(batch)) if samples is None else list(samples)
+    gp = np.zeros_like(p)
+    dat = None if data is None else np.asarray(data, float)
+    gd = None if dat is None else np.zeros_like(dat)
+    P = circuit.n_params
+    pidx = list(range(P)) if param_subset is None else list(param_subset)
+
+    def L(pp, dd, bs):
+        E = forward(circuit, pp, dd, observables, batch, threads=threads, samples=bs)
+        return float(sum(np.dot(w[b], E[k]) for k, b in enumerate(bs)))
+
+    if p.ndim == 2:
+        for b in samples:
+            for j in pidx:
+                pp, pm = p.copy(), p.copy()
+                pp[b, j] += h
+                pm[b, j] -= h
+                gp[b, j] = (L(pp, dat, [b]) - L(pm, dat, [b])) / (2 * h)
+    else:
+        for j in pidx:
+            pp, pm = p.copy(), p.copy()
+            pp[j] += h
+            pm[j] -= h
+            gp[j] = (L(pp, dat, samples) - L(pm, dat, samples)) / (2 * h)
+    if dat is not None and with_data:
+        for b in samples:
+            for j in range(dat.shape[1]):
+                dp_, dm_ = dat.copy(), dat.copy()
+                dp_[b, j] += h
+                dm_[b, j] -= h
+                gd[b, j] = (L(p, dp_, [b]) - L(p, dm_, [b])) / (2 * h)
+    return gp, gd

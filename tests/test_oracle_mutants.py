@@ -1,0 +1,82 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check
+that the pins catch every one of them: a dropped term, a wrong sign, a
+wrong index or bit order, a transposed operand."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+import oracle_pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "dq_oracle.c")
+
+# (name, exact text in dq_oracle.c, replacement)
+MUTANTS = [
+    ("ry-sign", "U[0] = c; U[1] = -s; U[2] = s; U[3] = c;", "U[0] = c; U[1] = s; U[2] = -s; U[3] = c;"),
+    ("rx-sign", "U[0] = c; U[1] = -I * s; U[2] = -I * s;", "U[0] = c; U[1] = I * s; U[2] = I * s;"),
+    ("rz-sign", "U[0] = cexp(-I * theta / 2.0); U[3] = cexp(I * theta / 2.0);",
+     "U[0] = cexp(I * theta / 2.0); U[3] = cexp(-I * theta / 2.0);"),
+    ("full-angle", "double c = cos(theta / 2.0), s = sin(theta / 2.0);", "double c = cos(theta), s = sin(theta);"),
+    ("y-sign", "k = 1; U[1] = -I; U[2] = I;", "k = 1; U[1] = I; U[2] = -I;"),
+    ("h-sign", "U[2] = 1.0 / sqrt(2.0); U[3] = -1.0 / sqrt(2.0);", "U[2] = -1.0 / sqrt(2.0); U[3] = 1.0 / sqrt(2.0);"),
+    ("cnot-swapped-roles", "U[0 * 4 + 0] = 1.0; U[1 * 4 + 1] = 1.0; U[2 * 4 + 3] = 1.0; U[3 * 4 + 2] = 1.0;",
+     "U[0 * 4 + 0] = 1.0; U[1 * 4 + 3] = 1.0; U[2 * 4 + 2] = 1.0; U[3 * 4 + 1] = 1.0;"),
+    ("cz-wrong-corner", "U[0] = 1.0; U[5] = 1.0; U[10] = 1.0; U[15] = -1.0;",
+     "U[0] = -1.0; U[5] = 1.0; U[10] = 1.0; U[15] = 1.0;"),
+    ("cp-conj", "U[15] = cexp(I * theta);", "U[15] = cexp(-I * theta);"),
+    ("rzz-sign", "U[10] = cexp(I * theta / 2.0); U[15] = cexp(-I * theta / 2.0);",
+     "U[10] = cexp(-I * theta / 2.0); U[15] = cexp(I * theta / 2.0);"),
+    ("lsb-wire0", ["target_mask |= 1LL << (n - 1 - wires[t]);", "off[a] += 1LL << (n - 1 - wires[t]);"],
+     ["target_mask |= 1LL << wires[t];", "off[a] += 1LL << wires[t];"]),
+    ("matrix-transposed", "acc += U[r * dim + c] * in[c];", "acc += U[c * dim + r] * in[c];"),
+    ("subindex-order", "if ((a >> (k - 1 - t)) & 1)", "if ((a >> t) & 1)"),
+    ("dropped-conj", "acc += conj(psi[j]) * phi[j];", "acc += psi[j] * phi[j];"),
+    ("prob-wrong-half", "if (!(j & bit))", "if (j & bit)"),
+]
+
+
+def _build(tmp_path, name, old, new):
+    text = open(SRC).read()
+    olds, news = (old, new) if isinstance(old, list) else ([old], [new])
+    for o, nw in zip(olds, news):
+        assert text.count(o) == 1, "mutant %s: anchor text not found once" % name
+        text = text.replace(o, nw)
+    src = tmp_path / ("m_%s.c" % name)
+    src.write_text(text)
+    so = tmp_path / ("m_%s.so" % name)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", str(so), str(src), "-lm"])
+    return str(so)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, old, new):
+    so = _build(tmp_path, name, old, new)
+    tests_dir = os.path.dirname(os.path.abspath(__file__))
+    r = subprocess.run([sys.executable, "-c", _RUNNER, so], cwd=tests_dir, capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    caught = [l for l in r.stdout.splitlines() if l.startswith("CAUGHT")]
+    assert caught, "planted mistake %r passed every pin" % name
+
+
+_RUNNER = """
+import ctypes, os, sys
+sys.path.insert(0, os.path.dirname(os.getcwd()))
+sys.path.insert(0, os.getcwd())
+import oracle, oracle_pins
+real = oracle.lib()
+L = ctypes.CDLL(sys.argv[1])
+for fn in ("orc_gate_matrix", "orc_apply", "orc_run", "orc_pauli_expval", "orc_prob_zero"):
+    getattr(L, fn).argtypes = getattr(real, fn).argtypes
+    getattr(L, fn).restype = getattr(real, fn).restype
+oracle._lib = L
+for pin in oracle_pins.ALL_PINS:
+    try:
+        pin()
+    except Exception as e:
+        print("CAUGHT", pin.__name__, str(e)[:100].replace(chr(10), " "))
+"""

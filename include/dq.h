@@ -1,0 +1,205 @@
+/*
+ * dq.h -- C ABI of libdq, a gfx950 (MI355X) state-vector engine for batched
+ * parameterised qubit circuits: gate application, Pauli-sum expectation
+ * values and adjoint-method gradients.
+ *
+ * The operations follow the paper's qubit simulator (DeepQuantum, arXiv
+ * 2512.18995):
+ *   - a circuit is an ordered list of gates on wires, applied to a start
+ *     state:  |psi_M> = U_M ... U_1 |psi_0>           (section 4.1, eq. of
+ *     pure-state evolution; section 4.2, QubitCircuit API);
+ *   - gate angles are trainable parameters or encoded data
+ *     (section 4.2, listing code:qubitcircuit, "encode=True");
+ *   - observables are Pauli strings, one expectation per observable and per
+ *     batch sample, [batch, n_obs]             (section 4.2, expectation());
+ *   - gradients come from the adjoint differentiation method behind a
+ *     custom autograd Function               (section 7.2, distributed sim.);
+ *   - samples are processed as a batch       (section 4.3, batch processing).
+ *
+ * Conventions
+ *   - state layout: [batch][2^n] complex, (re, im) interleaved, complex64
+ *     (float2) or complex128 (double2), contiguous; sample b starts at
+ *     b * 2^n amplitudes.  Flat index j = sum_w bit_w * 2^(n-1-w): wire 0 is
+ *     the most significant bit (the leftmost ket factor);
+ *   - RX/RY/RZ(t) = exp(-i t P / 2), RZZ(t) = exp(-i t Z(x)Z / 2),
+ *     CP(t) = diag(1, 1, 1, e^{i t}) on (control, target), CNOT flips the
+ *     target where the control is 1, CZ negates |11>, H = (X + Z)/sqrt 2;
+ *   - a gate angle is  scale * value  with value = params[idx] (per sample
+ *     row when params_bstride != 0), data[idx] (per sample row when
+ *     data_bstride != 0), or 1 for fixed gates;
+ *   - params, data, expectations, gradient weights and gradients are float64
+ *     device arrays for both state types.  Gate matrices are formed in
+ *     double on the device and rounded once to the state's precision.
+ *
+ * Ownership and memory
+ *   - every device buffer passed in (state, params, data, outputs,
+ *     workspace) belongs to the caller; libdq never frees them;
+ *   - a plan / observable owns copies of the host arrays given at creation
+ *     and a small device buffer (op tables, fixed matrices) that it
+ *     allocates on its first use on a device and frees in *_destroy;
+ *   - nothing else is allocated: all scratch space is the caller's
+ *     workspace, sized by dq_workspace_size.
+ *
+ * Errors and asynchrony
+ *   - every call validates its arguments on the host before enqueueing any
+ *     work; on failure nothing is enqueued, the status is returned and
+ *     dq_last_error() describes it (thread-local, valid until the next call
+ *     on the same thread);
+ *   - device work is asynchronous on `stream` (a hipStream_t; NULL = the
+ *     null stream).  Faults of earlier device work surface as DQ_ERR_HIP on
+ *     a later call or at the caller's synchronisation;
+ *   - the functions are re-entrant for distinct plans; concurrent calls on
+ *     one plan are safe once it has been used once on each device.
+ */
+#ifndef DQ_H
+#define DQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DQ_VERSION 1
+#define DQ_MAX_QUBITS 34          /* 2^34 complex64 amplitudes = 137 GB */
+#define DQ_MAX_GATE_QUBITS 5
+
+typedef enum {
+    DQ_OK = 0,
+    DQ_ERR_INVALID_ARG = 1,    /* null pointer, bad wire, bad index, bad size */
+    DQ_ERR_UNSUPPORTED = 2,    /* op / dtype / combination not implemented */
+    DQ_ERR_WORKSPACE = 3,      /* ws_bytes smaller than dq_workspace_size */
+    DQ_ERR_OUT_OF_RANGE = 4,   /* qubit count or batch beyond the limits */
+    DQ_ERR_HIP = 5,            /* a HIP runtime call failed */
+    DQ_ERR_INTERNAL = 6
+} dq_status;
+
+typedef enum { DQ_C64 = 0, DQ_C128 = 1 } dq_dtype;
+
+typedef enum {
+    DQ_OP_H = 0, DQ_OP_X = 1, DQ_OP_Y = 2, DQ_OP_Z = 3,
+    DQ_OP_RX = 4, DQ_OP_RY = 5, DQ_OP_RZ = 6,
+    DQ_OP_CNOT = 7, DQ_OP_CZ = 8, DQ_OP_SWAP = 9,
+    DQ_OP_CP = 10, DQ_OP_RZZ = 11,
+    DQ_OP_UNITARY = 12          /* dense 2^nq x 2^nq matrix, nq = 1..5 */
+} dq_op;
+
+typedef enum { DQ_SRC_NONE = 0, DQ_SRC_PARAM = 1, DQ_SRC_DATA = 2 } dq_src;
+
+/* One gate of a circuit.  wires: (control, target) for CNOT / CZ / CP; for
+ * DQ_OP_UNITARY wires[0] is the most significant bit of the matrix index.
+ * matrix (UNITARY only): host pointer to 2^nq x 2^nq complex entries,
+ * row-major, (re, im) interleaved doubles; copied by dq_plan_create. */
+typedef struct {
+    int32_t op;
+    int32_t nq;
+    int32_t wires[DQ_MAX_GATE_QUBITS];
+    int32_t src;
+    int64_t idx;
+    double scale;
+    const double *matrix;
+} dq_gate;
+
+/* One Pauli string with a real coefficient: P = i^{|x&z|} X^x Z^z, i.e.
+ * bit w of xmask / zmask selects X / Z on wire w, both bits select Y. */
+typedef struct {
+    double coef;
+    uint64_t xmask;
+    uint64_t zmask;
+} dq_pauli_term;
+
+/* Planner options (NULL = defaults). */
+typedef struct {
+    int32_t fusion;       /* 1 (default): register-tile passes that apply many gates per
+                             state sweep; 0: the plain path, one kernel launch per gate */
+    int32_t tile_bits;    /* register-resident wires per tile: 0 = auto (5 for complex64,
+                             4 for complex128); 1..6 (complex128: 1..5) */
+    int32_t fold_init;    /* 1 (default): fold the leading one-qubit gates of every wire into
+                             the initial product-state write when applying from |0..0> */
+    int32_t dense_fuse;   /* 0 (default): off; 4 or 5: fuse runs of gates that stay on <= k
+                             wires into one dense 2^k x 2^k block applied on the matrix cores */
+} dq_options;
+
+typedef struct dq_plan_s *dq_plan;
+typedef struct dq_obs_s *dq_obs;
+
+/* Plan statistics, for tests and benchmarks. */
+typedef struct {
+    int32_t nqubits;
+    int32_t dtype;
+    int64_t ngates;
+    int64_t fwd_steps;        /* kernel sweeps of the state in dq_apply_circuit */
+    int64_t fwd_tile_passes;  /* of which register-tile passes */
+    int64_t fwd_dense_blocks; /* of which matrix-core dense blocks */
+    int64_t adj_steps;        /* sweeps of the (state, adjoint) pair in dq_adjoint_grad */
+    int64_t folded_gates;     /* gates folded into the initial product state */
+    int64_t grad_gates;       /* gate occurrences that carry a gradient */
+    int32_t tile_bits;
+} dq_plan_stats;
+
+/* Build a plan for an n-qubit circuit (host only; no device work).
+ * nparams / ndata: row lengths of params / data that gate idx refer to.
+ * Errors: DQ_ERR_INVALID_ARG for a bad gate (unknown op, wrong nq, wire out
+ * of range or repeated, idx out of range, NULL matrix), DQ_ERR_OUT_OF_RANGE
+ * for nqubits outside 1..DQ_MAX_QUBITS. */
+dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, int64_t ngates,
+                         int64_t nparams, int64_t ndata, dq_dtype dtype, const dq_options *opt);
+void dq_plan_destroy(dq_plan plan);
+dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out);
+
+/* Observables: nobs Pauli sums over the terms [obs_offsets[o], obs_offsets[o+1]).
+ * Host only; masks must not touch wires >= nqubits. */
+dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms,
+                        const int64_t *obs_offsets, int32_t nobs);
+void dq_obs_destroy(dq_obs obs);
+
+/* Workspace bytes needed by dq_apply_circuit / dq_expval (grad = 0) or
+ * dq_adjoint_grad (grad = 1) for this batch; per_sample = 1 when params or
+ * data differ per sample.  obs may be NULL when grad = 0 and no expval is
+ * taken.  The workspace is a caller-owned device buffer, 256-byte aligned. */
+dq_status dq_workspace_size(dq_plan plan, dq_obs obs, int64_t batch, int32_t per_sample,
+                            int32_t grad, size_t *bytes);
+
+/* state[b] = init (a device array of 2^n amplitudes) for every sample, or
+ * |0...0> when init is NULL. */
+dq_status dq_state_init(dq_plan plan, void *state, int64_t batch, const void *init, void *stream);
+
+/* Apply the plan's circuit to every sample of `state` in place (paper 4.1).
+ * from_zero = 1: the input contents are ignored and the circuit is applied
+ * to |0...0>, with the leading one-qubit gates of each wire folded into the
+ * first write of the state.  params: [P] (params_bstride = 0) or rows of
+ * params_bstride doubles per sample; data likewise.  ws: workspace of at
+ * least dq_workspace_size(plan, NULL, batch, per_sample, 0) bytes. */
+dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const double *params,
+                           int64_t params_bstride, const double *data, int64_t data_bstride,
+                           int32_t from_zero, void *ws, size_t ws_bytes, void *stream);
+
+/* out[b][o] = sum_k coef_k <psi_b| P_k |psi_b> over the terms of observable
+ * o (paper 4.2, expectation()).  out: device [batch][nobs] float64.
+ * Reductions are deterministic (fixed order, float64 across blocks). */
+dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, double *out,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint gradient (paper 7.2) of L = sum_{b,o} grad_out[b][o] E[b][o]
+ * where E is dq_expval of the final state.  `state` must hold the final
+ * states produced by dq_apply_circuit with the same params / data; it is
+ * overwritten (un-applied back towards the start state) unless
+ * preserve_state = 1, which keeps it at the cost of one more state of
+ * workspace.  grad_params: [P] when params_bstride = 0 (summed over the
+ * batch) or [batch][P]; grad_data (nullable): [D] when data_bstride = 0 or
+ * [batch][D].  Both are overwritten. */
+dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch,
+                          const double *params, int64_t params_bstride, const double *data,
+                          int64_t data_bstride, const double *grad_out, double *grad_params,
+                          double *grad_data, int32_t preserve_state, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* Description of the last error on this thread ("" after success). */
+const char *dq_last_error(void);
+int32_t dq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DQ_H */

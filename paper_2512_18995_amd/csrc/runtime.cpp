@@ -1,0 +1,936 @@
+// runtime.cpp -- host side of libdq: argument validation, the planner that
+// turns a gate list into register-tile passes, matrix slots, lazy device
+// upload of the plan tables, and the C ABI of include/dq.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dq.h"
+#include "dq_internal.h"
+
+using namespace dq;
+
+// ================================================================ errors
+namespace {
+thread_local std::string g_err;
+
+dq_status fail(dq_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+dq_status ok() {
+    g_err.clear();
+    return DQ_OK;
+}
+#define DQ_HIP(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail(DQ_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_rotation(int op) { return op == OP_RX || op == OP_RY || op == OP_RZ || op == OP_CP || op == OP_RZZ; }
+int arity(int op) {
+    switch (op) {
+    case OP_CNOT: case OP_CZ: case OP_SWAP: case OP_CP: case OP_RZZ: return 2;
+    case OP_UNITARY: return -1;
+    default: return 1;
+    }
+}
+bool is_diag1(int op) { return op == OP_RZ || op == OP_Z; }
+int gen_of(int op) {
+    switch (op) {
+    case OP_RX: return GEN_X;
+    case OP_RY: return GEN_Y;
+    case OP_RZ: return GEN_Z;
+    case OP_RZZ: return GEN_ZZ;
+    case OP_CP: return GEN_P11;
+    default: return GEN_NONE;
+    }
+}
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ================================================================ plan
+enum StepKind { ST_TILE = 0, ST_G1, ST_CNOT, ST_CZ, ST_GK, ST_GRAD };
+
+struct Step {
+    int kind = 0;
+    int R = 0;
+    int32_t rbits[MAX_TILE_R] = {0};
+    int64_t op0 = 0, nops = 0;      // into plan.ops
+    int64_t ls0 = 0, nls = 0;       // into plan.lsg
+    int k = 0;
+    int32_t bits[5] = {0};          // per-gate: physical bits, bits[0] = matrix MSB / control
+    int64_t slot = 0;
+    int gen = 0, gslot = -1;
+};
+
+struct Program {
+    std::vector<Step> steps;
+    int64_t slot_lo = 0, slot_hi = 0;  // slot index range used (for prepare)
+    int64_t tile_passes = 0;
+};
+
+struct DevData {
+    void *blob = nullptr;
+    DGate *gates = nullptr;
+    double2 *fixed = nullptr;
+    DSlot *slots = nullptr;
+    TOp *ops = nullptr;
+    int32_t *lsg = nullptr;
+    int64_t *fold = nullptr;
+    int64_t *poff = nullptr, *doff = nullptr;
+    int32_t *pg = nullptr, *dg = nullptr;
+    double *pf = nullptr, *df = nullptr;
+};
+
+}  // namespace
+
+struct dq_plan_s {
+    int n = 0;
+    int dbl = 0;
+    dq_options opt{};
+    int64_t nparams = 0, ndata = 0;
+    std::vector<DGate> gates;
+    std::vector<double2> fixed;
+    std::vector<DSlot> slots;
+    int64_t block = 0;                  // complex elements per sample's matrix block
+    std::vector<TOp> ops;
+    std::vector<int32_t> lsg;
+    Program fwd_full, fwd_fold, adj;
+    bool has_fold = false;
+    std::vector<int64_t> fold_off;      // per physical bit: slot offset of the folded column, -1 none
+    int64_t folded_gates = 0;
+    int R_fwd = 0, R_adj = 0;
+    int32_t ngrad = 0;
+    std::vector<int64_t> poff, doff;
+    std::vector<int32_t> pg, dg;
+    std::vector<double> pf, df;
+    std::mutex mu;
+    std::map<int, DevData> dev;
+};
+
+struct dq_obs_s {
+    int n = 0;
+    int nobs = 0;
+    std::vector<DGroup> groups;
+    std::vector<DTerm> terms;
+    size_t og = 0, ot = 0;       // byte offsets of groups / terms in the device copy
+    std::mutex mu;
+    std::map<int, void *> dev;   // device -> [groups][terms]
+};
+
+namespace {
+
+// ---------------------------------------------------------------- slots
+int64_t add_slot(dq_plan_s &p, int dim, const std::vector<int> &factors, int dagger) {
+    DSlot s{};
+    s.dim = dim;
+    s.nf = (int32_t)factors.size();
+    for (size_t i = 0; i < factors.size(); ++i) s.f[i] = factors[i];
+    s.dagger = dagger;
+    s.off = p.block;
+    p.block += (int64_t)dim * dim;
+    p.slots.push_back(s);
+    return (int64_t)p.slots.size() - 1;
+}
+
+// ---------------------------------------------------------------- planner
+struct Planner {
+    dq_plan_s &p;
+    bool adjoint;
+    int R;
+    explicit Planner(dq_plan_s &pl, bool adj, int r) : p(pl), adjoint(adj), R(r) {}
+
+    void gbits(int g, int *q, int &nq) const {
+        nq = p.gates[g].nq;
+        for (int i = 0; i < nq; ++i) q[i] = p.gates[g].bits[i];
+    }
+    bool tile_ok(int g) const {
+        if (R <= 0) return false;
+        const DGate &G = p.gates[g];
+        if (G.op == OP_UNITARY && G.nq != 1) return false;
+        int hi = 0;
+        for (int i = 0; i < G.nq; ++i) hi += G.bits[i] >= 6;
+        return hi <= R;
+    }
+    bool diff(int g) const { return adjoint && p.gates[g].src != SRC_NONE && is_rotation(p.gates[g].op); }
+
+    // Greedy in-order selection of the gates one tile pass can execute when
+    // the register bits are S (grown up to R bits while scanning).  Returns
+    // the executed gate positions (indices into `rem`).
+    std::vector<int> select(const std::vector<int> &rem, uint64_t &S, int seed) const {
+        uint64_t blocked = 0;
+        std::vector<int> out;
+        int lslots = 0;
+        auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
+        if (seed >= 0) {
+            int q[5], nq;
+            gbits(rem[seed], q, nq);
+            for (int i = 0; i < nq; ++i)
+                if (q[i] >= 6) S |= 1ull << q[i];
+            if (popc(S) > R) return out;
+        }
+        for (size_t r = 0; r < rem.size(); ++r) {
+            const int g = rem[r];
+            int q[5], nq;
+            gbits(g, q, nq);
+            uint64_t Q = 0, need = 0;
+            for (int i = 0; i < nq; ++i) {
+                Q |= 1ull << q[i];
+                if (q[i] >= 6) need |= 1ull << q[i];
+            }
+            if ((Q & blocked) || !tile_ok(g) || (diff(g) && lslots >= 32) || popc(S | need) > R) {
+                blocked |= Q;
+                continue;
+            }
+            S |= need;
+            out.push_back((int)r);
+            if (diff(g)) ++lslots;
+        }
+        return out;
+    }
+
+    void emit_pergate(Program &prog, int g) {
+        const DGate &G = p.gates[g];
+        if (adjoint && diff(g)) {
+            Step gs;
+            gs.kind = ST_GRAD;
+            gs.gen = gen_of(G.op);
+            gs.bits[0] = G.bits[0];
+            gs.bits[1] = G.nq > 1 ? G.bits[1] : 0;
+            gs.gslot = grad_slot(g);
+            prog.steps.push_back(gs);
+        }
+        Step s;
+        s.k = G.nq;
+        for (int i = 0; i < G.nq; ++i) s.bits[i] = G.bits[i];
+        if (G.op == OP_CNOT) {
+            s.kind = ST_CNOT;
+        } else if (G.op == OP_CZ) {
+            s.kind = ST_CZ;
+        } else {
+            s.kind = G.nq == 1 ? ST_G1 : ST_GK;
+            s.slot = p.slots[add_slot(p, 1 << G.nq, {g}, adjoint ? 1 : 0)].off;
+        }
+        prog.steps.push_back(s);
+    }
+
+    std::vector<int> gslot_of;   // gate -> gradient slot
+    int grad_slot(int g) const { return gslot_of[g]; }
+
+    void plan(Program &prog, std::vector<int> order, bool fuse_1q) {
+        prog.slot_lo = (int64_t)p.slots.size();
+        std::vector<int> rem = order;
+        while (!rem.empty()) {
+            const int g0 = rem[0];
+            if (!tile_ok(g0)) {
+                emit_pergate(prog, g0);
+                rem.erase(rem.begin());
+                continue;
+            }
+            // candidate register sets: unseeded, and seeded by each of the
+            // first few gates that need non-lane bits
+            uint64_t bestS = 0;
+            std::vector<int> best;
+            {
+                uint64_t S = 0;
+                best = select(rem, S, -1);
+                bestS = S;
+            }
+            int tried = 0;
+            for (size_t r = 0; r < rem.size() && tried < 48; ++r) {
+                const DGate &G = p.gates[rem[r]];
+                bool hi = false;
+                for (int i = 0; i < G.nq; ++i) hi |= G.bits[i] >= 6;
+                if (!hi || !tile_ok(rem[r])) continue;
+                ++tried;
+                uint64_t S = 0;
+                std::vector<int> sel = select(rem, S, (int)r);
+                if (sel.size() > best.size()) {
+                    best = sel;
+                    bestS = S;
+                }
+            }
+            if (best.empty()) {            // nothing fits a tile: keep making progress
+                emit_pergate(prog, g0);
+                rem.erase(rem.begin());
+                continue;
+            }
+            // pad the register set to exactly R bits
+            for (int b = 6; b < p.n && __builtin_popcountll(bestS) < R; ++b) bestS |= 1ull << b;
+            Step st;
+            st.kind = ST_TILE;
+            st.R = R;
+            int nr = 0, local[64];
+            for (int b = 0; b < 64; ++b) local[b] = -1;
+            for (int b = 0; b < 6; ++b) local[b] = b;
+            for (int b = 6; b < p.n; ++b)
+                if (bestS >> b & 1) {
+                    st.rbits[nr] = b;
+                    local[b] = 6 + nr;
+                    ++nr;
+                }
+            st.op0 = (int64_t)p.ops.size();
+            st.ls0 = (int64_t)p.lsg.size();
+            std::vector<int> last_op(64, -1);     // per physical bit: index (in p.ops) of the last op touching it
+            std::vector<int64_t> op_slot;         // per op of this pass: its slot index, -1 none
+            for (int r : best) {
+                const int g = rem[r];
+                const DGate &G = p.gates[g];
+                TOp op{};
+                int64_t slot_idx = -1;
+                op.q0 = local[G.bits[0]];
+                op.q1 = G.nq > 1 ? local[G.bits[1]] : 0;
+                op.gen = GEN_NONE;
+                op.lslot = -1;
+                if (G.nq == 1) {
+                    const int prev = last_op[G.bits[0]];
+                    if (fuse_1q && prev >= st.op0 && (p.ops[prev].kind == TK_1Q || p.ops[prev].kind == TK_1QDIAG)) {
+                        DSlot &sl = p.slots[op_slot[prev - st.op0]];
+                        if (sl.nf < SLOT_MAXF) {   // fold into the previous one-qubit slot of this bit
+                            sl.f[sl.nf++] = g;
+                            if (!is_diag1(G.op)) p.ops[prev].kind = TK_1Q;
+                            continue;
+                        }
+                    }
+                    op.kind = is_diag1(G.op) ? TK_1QDIAG : TK_1Q;
+                    slot_idx = add_slot(p, 2, {g}, adjoint ? 1 : 0);
+                    op.slot = (int32_t)p.slots[slot_idx].off;
+                } else {
+                    switch (G.op) {
+                    case OP_CNOT: op.kind = TK_CNOT; break;
+                    case OP_CZ: op.kind = TK_CZ; break;
+                    case OP_SWAP: op.kind = TK_SWAP; break;
+                    default:
+                        op.kind = TK_2QDIAG;
+                        slot_idx = add_slot(p, 4, {g}, adjoint ? 1 : 0);
+                        op.slot = (int32_t)p.slots[slot_idx].off;
+                        break;
+                    }
+                }
+                if (diff(g)) {
+                    op.gen = gen_of(G.op);
+                    op.lslot = (int32_t)((int64_t)p.lsg.size() - st.ls0);
+                    p.lsg.push_back(grad_slot(g));
+                }
+                for (int i = 0; i < G.nq; ++i) last_op[G.bits[i]] = (int)p.ops.size();
+                p.ops.push_back(op);
+                op_slot.push_back(slot_idx);
+            }
+            st.nops = (int64_t)p.ops.size() - st.op0;
+            st.nls = (int64_t)p.lsg.size() - st.ls0;
+            prog.steps.push_back(st);
+            ++prog.tile_passes;
+            std::vector<char> done(rem.size(), 0);
+            for (int r : best) done[r] = 1;
+            std::vector<int> nrem;
+            for (size_t r = 0; r < rem.size(); ++r)
+                if (!done[r]) nrem.push_back(rem[r]);
+            rem.swap(nrem);
+        }
+        prog.slot_hi = (int64_t)p.slots.size();
+    }
+};
+
+int default_R(const dq_plan_s &p) {
+    // defaults keep two resident waves per SIMD (complex64: 32 amplitudes per
+    // lane, complex128: 16)
+    int R = p.opt.tile_bits > 0 ? p.opt.tile_bits : (p.dbl ? 4 : 5);
+    if (p.dbl && R > 5) R = 5;
+    if (R > p.n - 6) R = p.n - 6;
+    return R < 0 ? 0 : R;
+}
+
+dq_status build_plan(dq_plan_s &p) {
+    const int G = (int)p.gates.size();
+    const bool fused = p.opt.fusion != 0;
+    p.R_fwd = fused ? default_R(p) : 0;
+    p.R_adj = std::min(p.R_fwd, p.dbl ? 3 : 4);   // two states per tile in the adjoint
+    // gradient slots: every differentiable gate occurrence, in gate order
+    std::vector<int> gslot(G, -1);
+    p.ngrad = 0;
+    for (int g = 0; g < G; ++g)
+        if (p.gates[g].src != SRC_NONE && is_rotation(p.gates[g].op)) gslot[g] = p.ngrad++;
+    // CSR: parameter / data -> gradient slots with chain factors
+    auto csr = [&](int src, int64_t count, std::vector<int64_t> &off, std::vector<int32_t> &gi,
+                   std::vector<double> &f) {
+        std::vector<std::vector<std::pair<int, double>>> lists((size_t)count);
+        for (int g = 0; g < G; ++g)
+            if (gslot[g] >= 0 && p.gates[g].src == src)
+                lists[(size_t)p.gates[g].idx].push_back(
+                    {gslot[g], p.gates[g].scale * (p.gates[g].op == OP_CP ? -2.0 : 1.0)});
+        off.assign((size_t)count + 1, 0);
+        for (int64_t i = 0; i < count; ++i) {
+            off[i + 1] = off[i] + (int64_t)lists[i].size();
+            for (auto &e : lists[i]) {
+                gi.push_back(e.first);
+                f.push_back(e.second);
+            }
+        }
+    };
+    csr(SRC_PARAM, p.nparams, p.poff, p.pg, p.pf);
+    csr(SRC_DATA, p.ndata, p.doff, p.dg, p.df);
+
+    std::vector<int> order(G);
+    for (int g = 0; g < G; ++g) order[g] = g;
+    // forward, all gates
+    {
+        Planner pl(p, false, p.R_fwd);
+        pl.gslot_of = gslot;
+        pl.plan(p.fwd_full, order, true);
+    }
+    // forward from |0..0> with the leading one-qubit gates of every wire folded
+    p.fold_off.assign(p.n, -1);
+    p.has_fold = false;
+    p.folded_gates = 0;
+    if (fused && p.opt.fold_init) {
+        std::vector<std::vector<int>> lead(p.n);
+        std::vector<char> closed(p.n, 0), folded(G, 0);
+        for (int g = 0; g < G; ++g) {
+            const DGate &D = p.gates[g];
+            if (D.nq == 1) {
+                const int b = D.bits[0];
+                if (!closed[b] && (int)lead[b].size() < SLOT_MAXF) {
+                    lead[b].push_back(g);
+                    folded[g] = 1;
+                } else {
+                    closed[b] = 1;
+                }
+            } else {
+                for (int i = 0; i < D.nq; ++i) closed[D.bits[i]] = 1;
+            }
+        }
+        for (int b = 0; b < p.n; ++b)
+            if (!lead[b].empty()) {
+                p.fold_off[b] = p.slots[add_slot(p, 2, lead[b], 0)].off;
+                p.folded_gates += (int64_t)lead[b].size();
+            }
+        if (p.folded_gates > 0) {
+            p.has_fold = true;
+            std::vector<int> rest;
+            for (int g = 0; g < G; ++g)
+                if (!folded[g]) rest.push_back(g);
+            Planner pl(p, false, p.R_fwd);
+            pl.gslot_of = gslot;
+            const int64_t lo = (int64_t)p.slots.size() - (int64_t)std::count_if(p.fold_off.begin(), p.fold_off.end(),
+                                                                                [](int64_t o) { return o >= 0; });
+            pl.plan(p.fwd_fold, rest, true);
+            p.fwd_fold.slot_lo = lo;
+        }
+    }
+    // adjoint: the reversed gate list, daggers, no fusion of one-qubit gates
+    {
+        std::vector<int> rev(order.rbegin(), order.rend());
+        Planner pl(p, true, p.R_adj);
+        pl.gslot_of = gslot;
+        pl.plan(p.adj, rev, false);
+    }
+    return DQ_OK;
+}
+
+// ---------------------------------------------------------------- device upload
+template <typename T>
+size_t put(std::vector<char> &blob, const std::vector<T> &v) {
+    const size_t off = align256(blob.size());
+    blob.resize(off + std::max<size_t>(v.size() * sizeof(T), 1));
+    if (!v.empty()) memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+dq_status ensure_device(dq_plan_s &p, DevData **out) {
+    int dev = 0;
+    DQ_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(p.mu);
+    auto it = p.dev.find(dev);
+    if (it != p.dev.end()) {
+        *out = &it->second;
+        return DQ_OK;
+    }
+    std::vector<char> blob;
+    const size_t o_g = put(blob, p.gates), o_f = put(blob, p.fixed), o_s = put(blob, p.slots),
+                 o_o = put(blob, p.ops), o_l = put(blob, p.lsg), o_fo = put(blob, p.fold_off),
+                 o_po = put(blob, p.poff), o_pg = put(blob, p.pg), o_pf = put(blob, p.pf),
+                 o_do = put(blob, p.doff), o_dg = put(blob, p.dg), o_df = put(blob, p.df);
+    void *d = nullptr;
+    DQ_HIP(hipMalloc(&d, blob.size()));
+    hipError_t e = hipMemcpy(d, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(DQ_ERR_HIP, "plan upload: %s", hipGetErrorString(e));
+    }
+    DevData dd;
+    char *b = (char *)d;
+    dd.blob = d;
+    dd.gates = (DGate *)(b + o_g);
+    dd.fixed = (double2 *)(b + o_f);
+    dd.slots = (DSlot *)(b + o_s);
+    dd.ops = (TOp *)(b + o_o);
+    dd.lsg = (int32_t *)(b + o_l);
+    dd.fold = (int64_t *)(b + o_fo);
+    dd.poff = (int64_t *)(b + o_po);
+    dd.pg = (int32_t *)(b + o_pg);
+    dd.pf = (double *)(b + o_pf);
+    dd.doff = (int64_t *)(b + o_do);
+    dd.dg = (int32_t *)(b + o_dg);
+    dd.df = (double *)(b + o_df);
+    *out = &(p.dev[dev] = dd);
+    return DQ_OK;
+}
+
+dq_status ensure_obs(dq_obs_s &o, const DGroup **groups, const DTerm **terms) {
+    int dev = 0;
+    DQ_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(o.mu);
+    auto it = o.dev.find(dev);
+    if (it == o.dev.end()) {
+        std::vector<char> blob;
+        o.og = put(blob, o.groups);
+        o.ot = put(blob, o.terms);
+        void *d = nullptr;
+        DQ_HIP(hipMalloc(&d, blob.size()));
+        hipError_t e = hipMemcpy(d, blob.data(), blob.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return fail(DQ_ERR_HIP, "observable upload: %s", hipGetErrorString(e));
+        }
+        it = o.dev.emplace(dev, d).first;
+    }
+    char *b = (char *)it->second;
+    *groups = (const DGroup *)(b + o.og);
+    *terms = (const DTerm *)(b + o.ot);
+    return DQ_OK;
+}
+
+// ---------------------------------------------------------------- sizes
+int64_t expval_blocks(int n, int64_t batch) {
+    const int64_t N = int64_t(1) << n;
+    int64_t eb = N / (256 * 64);
+    const int64_t cap = std::max<int64_t>(1, 2048 / batch);
+    eb = std::min(eb, cap);
+    return std::max<int64_t>(eb, 1);
+}
+
+int64_t grad_waves(const dq_plan_s &p, int64_t batch) {
+    int64_t units;
+    if (p.R_adj > 0) units = int64_t(1) << (p.n - 6 - p.R_adj);      // tiles per sample
+    else units = std::max<int64_t>(1, (int64_t(1) << p.n) / (256 * 16));
+    const int64_t cap = std::max<int64_t>(1, 4096 / batch);
+    return std::max<int64_t>(1, std::min(units, cap));
+}
+
+struct WsLayout {
+    size_t mats = 0, expv = 0, lam = 0, keep = 0, part = 0, total = 0;
+};
+
+WsLayout layout(const dq_plan_s &p, const dq_obs_s *o, int64_t batch, int per_sample, int grad) {
+    WsLayout L;
+    const size_t amp = p.dbl ? 16 : 8;
+    const int64_t bm = per_sample ? batch : 1;
+    size_t off = 0;
+    L.mats = off;
+    off = align256(off + (size_t)bm * (size_t)std::max<int64_t>(p.block, 1) * amp);
+    L.expv = off;
+    if (o) off = align256(off + (size_t)batch * expval_blocks(p.n, batch) * std::max<size_t>(o->terms.size(), 1) * 16);
+    L.lam = off;
+    const size_t sbytes = (size_t)batch * ((size_t)1 << p.n) * amp;
+    if (grad) off = align256(off + sbytes);
+    L.keep = off;
+    if (grad == 2) off = align256(off + sbytes);
+    L.part = off;
+    if (grad) off = align256(off + (size_t)batch * grad_waves(p, batch) * std::max<int32_t>(p.ngrad, 1) * 8);
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------- execution
+dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, void *lam, int64_t batch,
+                      const void *mats, int64_t mstride, double *partial, int wps, hipStream_t s) {
+    for (const Step &S : prog.steps) {
+        hipError_t e = hipSuccess;
+        switch (S.kind) {
+        case ST_TILE: {
+            TileArgs a{};
+            a.st = st;
+            a.lam = lam;
+            a.n = p.n;
+            a.R = S.R;
+            for (int i = 0; i < MAX_TILE_R; ++i) a.rbits[i] = S.rbits[i];
+            a.batch = batch;
+            a.ops = d.ops + S.op0;
+            a.nops = (int32_t)S.nops;
+            a.nlslots = (int32_t)S.nls;
+            a.mats = mats;
+            a.mstride = mstride;
+            a.partial = partial;
+            a.lslot_gslot = d.lsg + S.ls0;
+            a.wps = wps;
+            a.ngrad = p.ngrad;
+            e = lam ? launch_tile_adj(p.dbl, a, s) : launch_tile_fwd(p.dbl, a, s);
+            break;
+        }
+        case ST_GRAD:
+            e = launch_grad_gate(p.dbl, st, lam, p.n, batch, S.gen, S.bits[0], S.bits[1], partial, wps, p.ngrad,
+                                 S.gslot, s);
+            break;
+        default:
+            for (int which = 0; which < (lam ? 2 : 1) && e == hipSuccess; ++which) {
+                void *x = which ? lam : st;
+                switch (S.kind) {
+                case ST_G1: e = launch_gate1(p.dbl, x, p.n, batch, S.bits[0], mats, mstride, S.slot, s); break;
+                case ST_CNOT: e = launch_cnot(p.dbl, x, p.n, batch, S.bits[0], S.bits[1], s); break;
+                case ST_CZ: e = launch_cz(p.dbl, x, p.n, batch, S.bits[0], S.bits[1], s); break;
+                default: e = launch_gatek(p.dbl, x, p.n, batch, S.k, S.bits, mats, mstride, S.slot, s); break;
+                }
+            }
+            break;
+        }
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+    }
+    return DQ_OK;
+}
+
+dq_status check_batch(const dq_plan_s &p, int64_t batch) {
+    if (batch < 1) return fail(DQ_ERR_INVALID_ARG, "batch must be >= 1 (got %lld)", (long long)batch);
+    if (batch > 65535) return fail(DQ_ERR_OUT_OF_RANGE, "batch %lld exceeds 65535", (long long)batch);
+    const double bytes = (double)batch * std::ldexp(1.0, p.n) * (p.dbl ? 16 : 8);
+    if (bytes > 512e9) return fail(DQ_ERR_OUT_OF_RANGE, "batch x 2^n state of %.3g bytes exceeds device memory", bytes);
+    return DQ_OK;
+}
+
+dq_status check_sources(const dq_plan_s &p, const double *params, int64_t pstride, const double *data, int64_t dstride) {
+    if (p.nparams > 0 && !params) return fail(DQ_ERR_INVALID_ARG, "params is NULL but the circuit reads %lld parameters", (long long)p.nparams);
+    if (p.ndata > 0 && !data) return fail(DQ_ERR_INVALID_ARG, "data is NULL but the circuit reads %lld data columns", (long long)p.ndata);
+    if (pstride != 0 && pstride < p.nparams) return fail(DQ_ERR_INVALID_ARG, "params_bstride %lld < nparams %lld", (long long)pstride, (long long)p.nparams);
+    if (dstride != 0 && dstride < p.ndata) return fail(DQ_ERR_INVALID_ARG, "data_bstride %lld < ndata %lld", (long long)dstride, (long long)p.ndata);
+    if (pstride < 0 || dstride < 0) return fail(DQ_ERR_INVALID_ARG, "negative batch stride");
+    return DQ_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char *dq_last_error(void) { return g_err.c_str(); }
+int32_t dq_version(void) { return DQ_VERSION; }
+
+dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, int64_t ngates, int64_t nparams,
+                         int64_t ndata, dq_dtype dtype, const dq_options *opt) {
+    if (!out) return fail(DQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nqubits < 1 || nqubits > DQ_MAX_QUBITS)
+        return fail(DQ_ERR_OUT_OF_RANGE, "nqubits %d outside 1..%d", nqubits, DQ_MAX_QUBITS);
+    if (ngates < 0 || (ngates > 0 && !gates)) return fail(DQ_ERR_INVALID_ARG, "bad gate list");
+    if (ngates > (1 << 24)) return fail(DQ_ERR_OUT_OF_RANGE, "too many gates (%lld)", (long long)ngates);
+    if (nparams < 0 || ndata < 0) return fail(DQ_ERR_INVALID_ARG, "negative nparams / ndata");
+    if (dtype != DQ_C64 && dtype != DQ_C128) return fail(DQ_ERR_UNSUPPORTED, "dtype %d", (int)dtype);
+    dq_options o{1, 0, 1, 0};
+    if (opt) o = *opt;
+    if (o.tile_bits < 0 || o.tile_bits > 6) return fail(DQ_ERR_INVALID_ARG, "tile_bits %d outside 0..6", o.tile_bits);
+    if (o.dense_fuse != 0) return fail(DQ_ERR_UNSUPPORTED, "dense_fuse is not available in this build");
+    auto *p = new dq_plan_s();
+    p->n = nqubits;
+    p->dbl = dtype == DQ_C128;
+    p->opt = o;
+    p->nparams = nparams;
+    p->ndata = ndata;
+    for (int64_t g = 0; g < ngates; ++g) {
+        const dq_gate &G = gates[g];
+        if (G.op < DQ_OP_H || G.op > DQ_OP_UNITARY) {
+            delete p;
+            return fail(DQ_ERR_INVALID_ARG, "gate %lld: unknown op %d", (long long)g, G.op);
+        }
+        const int a = arity(G.op);
+        if ((a > 0 && G.nq != a) || (a < 0 && (G.nq < 1 || G.nq > DQ_MAX_GATE_QUBITS))) {
+            delete p;
+            return fail(DQ_ERR_INVALID_ARG, "gate %lld: op %d with %d wires", (long long)g, G.op, G.nq);
+        }
+        for (int i = 0; i < G.nq; ++i) {
+            if (G.wires[i] < 0 || G.wires[i] >= nqubits) {
+                delete p;
+                return fail(DQ_ERR_INVALID_ARG, "gate %lld: wire %d outside 0..%d", (long long)g, G.wires[i], nqubits - 1);
+            }
+            for (int j = 0; j < i; ++j)
+                if (G.wires[j] == G.wires[i]) {
+                    delete p;
+                    return fail(DQ_ERR_INVALID_ARG, "gate %lld: wire %d repeated", (long long)g, G.wires[i]);
+                }
+        }
+        if (G.src < DQ_SRC_NONE || G.src > DQ_SRC_DATA) {
+            delete p;
+            return fail(DQ_ERR_INVALID_ARG, "gate %lld: bad angle source %d", (long long)g, G.src);
+        }
+        if (G.src != DQ_SRC_NONE && !is_rotation(G.op)) {
+            delete p;
+            return fail(DQ_ERR_INVALID_ARG, "gate %lld: op %d takes no angle", (long long)g, G.op);
+        }
+        if ((G.src == DQ_SRC_PARAM && (G.idx < 0 || G.idx >= nparams)) ||
+            (G.src == DQ_SRC_DATA && (G.idx < 0 || G.idx >= ndata))) {
+            delete p;
+            return fail(DQ_ERR_INVALID_ARG, "gate %lld: source index %lld out of range", (long long)g, (long long)G.idx);
+        }
+        if (!std::isfinite(G.scale)) {
+            delete p;
+            return fail(DQ_ERR_INVALID_ARG, "gate %lld: non-finite scale", (long long)g);
+        }
+        DGate D{};
+        D.op = G.op;
+        D.nq = G.nq;
+        for (int i = 0; i < G.nq; ++i) D.bits[i] = nqubits - 1 - G.wires[i];
+        D.src = G.src;
+        D.idx = G.idx;
+        D.scale = G.scale;
+        D.mat_off = -1;
+        if (G.op == DQ_OP_UNITARY) {
+            if (!G.matrix) {
+                delete p;
+                return fail(DQ_ERR_INVALID_ARG, "gate %lld: UNITARY without a matrix", (long long)g);
+            }
+            const int dim = 1 << G.nq;
+            D.mat_off = (int64_t)p->fixed.size();
+            for (int i = 0; i < dim * dim; ++i) p->fixed.push_back(double2{G.matrix[2 * i], G.matrix[2 * i + 1]});
+        }
+        p->gates.push_back(D);
+    }
+    dq_status st = build_plan(*p);
+    if (st != DQ_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return ok();
+}
+
+void dq_plan_destroy(dq_plan plan) {
+    if (!plan) return;
+    for (auto &kv : plan->dev) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess) {
+            (void)hipSetDevice(kv.first);
+            (void)hipFree(kv.second.blob);
+            (void)hipSetDevice(cur);
+        }
+    }
+    delete plan;
+}
+
+dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) {
+    if (!plan || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    dq_plan_stats s{};
+    s.nqubits = plan->n;
+    s.dtype = plan->dbl ? DQ_C128 : DQ_C64;
+    s.ngates = (int64_t)plan->gates.size();
+    const Program &f = plan->has_fold ? plan->fwd_fold : plan->fwd_full;
+    s.fwd_steps = (int64_t)f.steps.size() + (plan->has_fold ? 1 : 0);
+    s.fwd_tile_passes = f.tile_passes;
+    s.fwd_dense_blocks = 0;
+    s.adj_steps = (int64_t)plan->adj.steps.size();
+    s.folded_gates = plan->folded_gates;
+    s.grad_gates = plan->ngrad;
+    s.tile_bits = plan->R_fwd;
+    *out = s;
+    return ok();
+}
+
+dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms, const int64_t *obs_offsets,
+                        int32_t nobs) {
+    if (!out) return fail(DQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nqubits < 1 || nqubits > DQ_MAX_QUBITS) return fail(DQ_ERR_OUT_OF_RANGE, "nqubits %d", nqubits);
+    if (nobs < 1 || !obs_offsets) return fail(DQ_ERR_INVALID_ARG, "need nobs >= 1 and obs_offsets");
+    if (obs_offsets[0] != 0) return fail(DQ_ERR_INVALID_ARG, "obs_offsets[0] must be 0");
+    for (int o = 0; o < nobs; ++o)
+        if (obs_offsets[o + 1] < obs_offsets[o]) return fail(DQ_ERR_INVALID_ARG, "obs_offsets not ascending");
+    const int64_t nterms = obs_offsets[nobs];
+    if (nterms > 0 && !terms) return fail(DQ_ERR_INVALID_ARG, "terms is NULL");
+    if (nterms > (1 << 20)) return fail(DQ_ERR_OUT_OF_RANGE, "too many terms");
+    const uint64_t valid = nqubits >= 64 ? ~0ull : ((1ull << nqubits) - 1);
+    auto *o = new dq_obs_s();
+    o->n = nqubits;
+    o->nobs = nobs;
+    struct Tm { uint64_t x, z; double c; int obs; };
+    std::vector<Tm> all;
+    for (int ob = 0; ob < nobs; ++ob)
+        for (int64_t t = obs_offsets[ob]; t < obs_offsets[ob + 1]; ++t) {
+            const dq_pauli_term &T = terms[t];
+            if ((T.xmask | T.zmask) & ~valid) {
+                delete o;
+                return fail(DQ_ERR_INVALID_ARG, "term %lld touches a wire >= %d", (long long)t, nqubits);
+            }
+            if (!std::isfinite(T.coef)) {
+                delete o;
+                return fail(DQ_ERR_INVALID_ARG, "term %lld: non-finite coefficient", (long long)t);
+            }
+            uint64_t px = 0, pz = 0;   // wire w -> physical bit n-1-w
+            for (int w = 0; w < nqubits; ++w) {
+                if (T.xmask >> w & 1) px |= 1ull << (nqubits - 1 - w);
+                if (T.zmask >> w & 1) pz |= 1ull << (nqubits - 1 - w);
+            }
+            all.push_back({px, pz, T.coef, ob});
+        }
+    std::stable_sort(all.begin(), all.end(), [](const Tm &a, const Tm &b) { return a.x < b.x; });
+    for (size_t i = 0; i < all.size(); ++i) {
+        if (o->groups.empty() || o->groups.back().xmask != all[i].x)
+            o->groups.push_back(DGroup{all[i].x, (int32_t)i, (int32_t)i});
+        o->groups.back().t1 = (int32_t)i + 1;
+        const int ny = __builtin_popcountll(all[i].x & all[i].z) & 3;   // i^{nY}
+        const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+        o->terms.push_back(DTerm{all[i].z, all[i].c * re[ny], all[i].c * im[ny], all[i].obs, 0});
+    }
+    *out = o;
+    return ok();
+}
+
+void dq_obs_destroy(dq_obs obs) {
+    if (!obs) return;
+    for (auto &kv : obs->dev) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess) {
+            (void)hipSetDevice(kv.first);
+            (void)hipFree(kv.second);
+            (void)hipSetDevice(cur);
+        }
+    }
+    delete obs;
+}
+
+dq_status dq_workspace_size(dq_plan plan, dq_obs obs, int64_t batch, int32_t per_sample, int32_t grad, size_t *bytes) {
+    if (!plan || !bytes) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (grad < 0 || grad > 2) return fail(DQ_ERR_INVALID_ARG, "grad must be 0, 1 or 2");
+    if (grad && !obs) return fail(DQ_ERR_INVALID_ARG, "the adjoint needs an observable");
+    dq_status st = check_batch(*plan, batch);
+    if (st != DQ_OK) return st;
+    *bytes = layout(*plan, obs, batch, per_sample ? 1 : 0, grad).total;
+    return ok();
+}
+
+dq_status dq_state_init(dq_plan plan, void *state, int64_t batch, const void *init, void *stream) {
+    if (!plan || !state) return fail(DQ_ERR_INVALID_ARG, "NULL plan or state");
+    dq_status st = check_batch(*plan, batch);
+    if (st != DQ_OK) return st;
+    hipError_t e = init ? launch_init_copy(plan->dbl, state, init, plan->n, batch, (hipStream_t)stream)
+                        : launch_init_zero(plan->dbl, state, plan->n, batch, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "state init: %s", hipGetErrorString(e));
+    return ok();
+}
+
+dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const double *params, int64_t params_bstride,
+                           const double *data, int64_t data_bstride, int32_t from_zero, void *ws, size_t ws_bytes,
+                           void *stream) {
+    if (!plan || !state) return fail(DQ_ERR_INVALID_ARG, "NULL plan or state");
+    dq_status st = check_batch(*plan, batch);
+    if (st != DQ_OK) return st;
+    if ((st = check_sources(*plan, params, params_bstride, data, data_bstride)) != DQ_OK) return st;
+    const int per_sample = (params_bstride != 0 || data_bstride != 0) ? 1 : 0;
+    const WsLayout L = layout(*plan, nullptr, batch, per_sample, 0);
+    if (!ws || ws_bytes < L.total)
+        return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : 0);
+    DevData *d = nullptr;
+    if ((st = ensure_device(*plan, &d)) != DQ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const bool fold = from_zero && plan->has_fold;
+    const Program &prog = fold ? plan->fwd_fold : plan->fwd_full;
+    const int64_t bm = per_sample ? batch : 1;
+    const int64_t mstride = per_sample ? plan->block : 0;
+    char *w = (char *)ws;
+    void *mats = w + L.mats;
+    hipError_t e = launch_prepare(plan->dbl, d->gates, d->fixed, d->slots + prog.slot_lo,
+                                  (int32_t)(prog.slot_hi - prog.slot_lo), params, params_bstride, data, data_bstride,
+                                  mats, plan->block, bm, s);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
+    if (fold) e = launch_init_product(plan->dbl, state, plan->n, batch, mats, mstride, d->fold, s);
+    else if (from_zero) e = launch_init_zero(plan->dbl, state, plan->n, batch, s);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "init: %s", hipGetErrorString(e));
+    if ((st = run_program(*plan, *d, prog, state, nullptr, batch, mats, mstride, nullptr, 0, s)) != DQ_OK) return st;
+    return ok();
+}
+
+dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, double *out, void *ws,
+                    size_t ws_bytes, void *stream) {
+    if (!plan || !obs || !state || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (obs->n != plan->n) return fail(DQ_ERR_INVALID_ARG, "observable is for %d qubits, plan for %d", obs->n, plan->n);
+    dq_status st = check_batch(*plan, batch);
+    if (st != DQ_OK) return st;
+    const WsLayout L = layout(*plan, obs, batch, 0, 0);
+    if (!ws || ws_bytes < L.total)
+        return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : 0);
+    const DGroup *g = nullptr;
+    const DTerm *t = nullptr;
+    if ((st = ensure_obs(*obs, &g, &t)) != DQ_OK) return st;
+    const int eb = (int)expval_blocks(plan->n, batch);
+    hipError_t e = launch_expval(plan->dbl, state, plan->n, batch, g, (int32_t)obs->groups.size(), t,
+                                 (int32_t)obs->terms.size(), obs->nobs, (double *)((char *)ws + L.expv), eb, out,
+                                 (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "expval: %s", hipGetErrorString(e));
+    return ok();
+}
+
+dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, const double *params,
+                          int64_t params_bstride, const double *data, int64_t data_bstride, const double *grad_out,
+                          double *grad_params, double *grad_data, int32_t preserve_state, void *ws, size_t ws_bytes,
+                          void *stream) {
+    if (!plan || !obs || !state || !grad_out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (obs->n != plan->n) return fail(DQ_ERR_INVALID_ARG, "observable is for %d qubits, plan for %d", obs->n, plan->n);
+    if (plan->nparams > 0 && !grad_params) return fail(DQ_ERR_INVALID_ARG, "grad_params is NULL");
+    dq_status st = check_batch(*plan, batch);
+    if (st != DQ_OK) return st;
+    if ((st = check_sources(*plan, params, params_bstride, data, data_bstride)) != DQ_OK) return st;
+    const int per_sample = (params_bstride != 0 || data_bstride != 0) ? 1 : 0;
+    const int grad = preserve_state ? 2 : 1;
+    const WsLayout L = layout(*plan, obs, batch, per_sample, grad);
+    if (!ws || ws_bytes < L.total)
+        return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : 0);
+    DevData *d = nullptr;
+    if ((st = ensure_device(*plan, &d)) != DQ_OK) return st;
+    const DGroup *g = nullptr;
+    const DTerm *t = nullptr;
+    if ((st = ensure_obs(*obs, &g, &t)) != DQ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    void *mats = w + L.mats;
+    void *lam = w + L.lam;
+    double *partial = (double *)(w + L.part);
+    const int64_t bm = per_sample ? batch : 1;
+    const int64_t mstride = per_sample ? plan->block : 0;
+    const int wps = (int)grad_waves(*plan, batch);
+    void *psi = state;
+    hipError_t e;
+    if (preserve_state) {
+        psi = w + L.keep;
+        e = launch_copy(plan->dbl, psi, state, batch << plan->n, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "copy: %s", hipGetErrorString(e));
+    }
+    e = launch_prepare(plan->dbl, d->gates, d->fixed, d->slots + plan->adj.slot_lo,
+                       (int32_t)(plan->adj.slot_hi - plan->adj.slot_lo), params, params_bstride, data, data_bstride,
+                       mats, plan->block, bm, s);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
+    e = launch_lambda(plan->dbl, psi, lam, plan->n, batch, g, (int32_t)obs->groups.size(), t, grad_out, obs->nobs, s);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "lambda: %s", hipGetErrorString(e));
+    if ((st = run_program(*plan, *d, plan->adj, psi, lam, batch, mats, mstride, partial, wps, s)) != DQ_OK) return st;
+    if (plan->nparams > 0) {
+        e = launch_grad_final(partial, batch, wps, plan->ngrad, d->poff, d->pg, d->pf, plan->nparams,
+                              params_bstride != 0 ? 1 : 0, grad_params, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "grad reduce: %s", hipGetErrorString(e));
+    }
+    if (grad_data && plan->ndata > 0) {
+        e = launch_grad_final(partial, batch, wps, plan->ngrad, d->doff, d->dg, d->df, plan->ndata,
+                              data_bstride != 0 ? 1 : 0, grad_data, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "grad reduce: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+"""Python face of libdq: plans, observables and the four hot-path calls.
+
+Thin wrappers: validation of tensor shapes / dtypes / devices, then one call
+into the C ABI with raw device pointers and torch's current HIP stream.
+PyTorch provides device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+CDTYPE = {"c64": torch.complex64, "c128": torch.complex128}
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Plan:
+    """A circuit planned for one qubit count and precision (host only until
+    its first use on a device)."""
+
+    def __init__(self, circuit, dtype: str = "c64", fusion: bool = True, tile_bits: int = 0,
+                 fold_init: bool = True):
+        self.n = int(circuit.n)
+        self.dtype = dtype
+        self.nparams = int(circuit.n_params)
+        self.ndata = int(circuit.n_data)
+        self.gates = list(circuit.gates)
+        arr, keep = _lib.gate_array(self.gates)
+        opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, 0)
+        h = ctypes.c_void_p()
+        check(lib().dq_plan_create(ctypes.byref(h), self.n, arr, len(self.gates), self.nparams, self.ndata,
+                                   _lib.C64 if dtype == "c64" else _lib.C128, ctypes.byref(opt)), "dq_plan_create")
+        self._h = h
+        del keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().dq_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def stats(self) -> dict:
+        s = _lib.DqPlanStats()
+        check(lib().dq_plan_get_stats(self._h, ctypes.byref(s)), "dq_plan_get_stats")
+        return {k: getattr(s, k) for k, _ in _lib.DqPlanStats._fields_}
+
+    def workspace_size(self, batch: int, per_sample: bool = False, grad: int = 0, obs: "Observable" = None) -> int:
+        n = ctypes.c_size_t(0)
+        check(lib().dq_workspace_size(self._h, obs.handle if obs else None, batch, 1 if per_sample else 0, grad,
+                                      ctypes.byref(n)), "dq_workspace_size")
+        return n.value
+
+    def state(self, batch: int, device="cuda") -> torch.Tensor:
+        return torch.empty((batch, 1 << self.n), dtype=CDTYPE[self.dtype], device=device)
+
+    def workspace(self, batch: int, per_sample=False, grad=0, obs=None, device="cuda") -> torch.Tensor:
+        return torch.empty(max(self.workspace_size(batch, per_sample, grad, obs), 1), dtype=torch.uint8,
+                           device=device)
+
+
+class Observable:
+    """nobs Pauli sums; each a list of (coef, letters) with letters[w] on wire w."""
+
+    def __init__(self, n: int, observables: Sequence):
+        self.n = int(n)
+        self.nobs = len(observables)
+        terms, off = _lib.pauli_arrays(self.n, observables)
+        h = ctypes.c_void_p()
+        check(lib().dq_obs_create(ctypes.byref(h), self.n, terms, off, self.nobs), "dq_obs_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().dq_obs_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def _check_state(plan: Plan, state: torch.Tensor):
+    if state.dtype != CDTYPE[plan.dtype] or not state.is_cuda or not state.is_contiguous():
+        raise ValueError("state must be a contiguous %s CUDA tensor" % CDTYPE[plan.dtype])
+    if state.dim() != 2 or state.shape[1] != (1 << plan.n):
+        raise ValueError("state must have shape [batch, 2^%d]" % plan.n)
+
+
+def _f64(t: Optional[torch.Tensor], device) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    t = t.detach()
+    if t.dtype != torch.float64 or t.device != torch.device(device) or not t.is_contiguous():
+        t = t.to(device=device, dtype=torch.float64).contiguous()
+    return t
+
+
+def _stride(t: Optional[torch.Tensor]) -> int:
+    return 0 if t is None or t.dim() < 2 else int(t.shape[1])
+
+
+def state_init(plan: Plan, state: torch.Tensor, init: Optional[torch.Tensor] = None):
+    _check_state(plan, state)
+    check(lib().dq_state_init(plan.handle, state.data_ptr(), state.shape[0], _ptr(init), _stream(state.device)),
+          "dq_state_init")
+
+
+def apply_circuit(plan: Plan, state: torch.Tensor, params=None, data=None, from_zero: bool = True,
+                  ws: Optional[torch.Tensor] = None):
+    """Apply the circuit to every sample of ``state`` in place.  ``params``:
+    [P] (shared) or [B, P]; ``data``: [B, D] or [D] (shared)."""
+    _check_state(plan, state)
+    dev = state.device
+    B = state.shape[0]
+    p, d = _f64(params, dev), _f64(data, dev)
+    per_sample = _stride(p) != 0 or _stride(d) != 0
+    if ws is None:
+        ws = plan.workspace(B, per_sample, 0, None, dev)
+    check(lib().dq_apply_circuit(plan.handle, state.data_ptr(), B, _ptr(p), _stride(p), _ptr(d), _stride(d),
+                                 1 if from_zero else 0, ws.data_ptr(), ws.numel(), _stream(dev)), "dq_apply_circuit")
+    return state
+
+
+def expval(plan: Plan, obs: Observable, state: torch.Tensor, ws: Optional[torch.Tensor] = None,
+           out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _check_state(plan, state)
+    dev = state.device
+    B = state.shape[0]
+    if out is None:
+        out = torch.empty((B, obs.nobs), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = plan.workspace(B, False, 0, obs, dev)
+    check(lib().dq_expval(plan.handle, obs.handle, state.data_ptr(), B, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                          _stream(dev)), "dq_expval")
+    return out
+
+
+def adjoint_grad(plan: Plan, obs: Observable, state: torch.Tensor, params, data, grad_out: torch.Tensor,
+                 preserve_state: bool = False, ws: Optional[torch.Tensor] = None, want_data: bool = True):
+    """VJP of sum_{b,o} grad_out[b,o] E[b,o] w.r.t. params and data (adjoint
+    sweep).  ``state`` must hold the final states; it is consumed unless
+    ``preserve_state``."""
+    _check_state(plan, state)
+    dev = state.device
+    B = state.shape[0]
+    p, d = _f64(params, dev), _f64(data, dev)
+    go = _f64(grad_out, dev)
+    if go.shape != (B, obs.nobs):
+        raise ValueError("grad_out must be [batch, nobs]")
+    per_sample = _stride(p) != 0 or _stride(d) != 0
+    if ws is None:
+        ws = plan.workspace(B, per_sample, 2 if preserve_state else 1, obs, dev)
+    gp = torch.empty_like(p) if p is not None else None
+    gd = torch.empty_like(d) if (d is not None and want_data) else None
+    check(lib().dq_adjoint_grad(plan.handle, obs.handle, state.data_ptr(), B, _ptr(p), _stride(p), _ptr(d),
+                                _stride(d), go.data_ptr(), _ptr(gp), _ptr(gd), 1 if preserve_state else 0,
+                                ws.data_ptr(), ws.numel(), _stream(dev)), "dq_adjoint_grad")
+    return gp, gd
+
+
+class ExpvalFunction(torch.autograd.Function):
+    """E[b, o] = <psi_b(params, data)| H_o |psi_b(...)> with the adjoint
+    method as its backward (the custom autograd Function of the paper's
+    distributed simulator, section 7.2, here on one GPU)."""
+
+    @staticmethod
+    def forward(ctx, params, data, plan: Plan, obs: Observable, batch: int):
+        dev = params.device if params is not None else data.device
+        state = plan.state(batch, dev)
+        apply_circuit(plan, state, params, data, from_zero=True)
+        E = expval(plan, obs, state)
+        ctx.plan, ctx.obs = plan, obs
+        ctx.save_for_backward(params, data, state)
+        return E
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        params, data, state = ctx.saved_tensors
+        want_data = data is not None and ctx.needs_input_grad[1]
+        gp, gd = adjoint_grad(ctx.plan, ctx.obs, state, params, data, grad_out, preserve_state=True,
+                              want_data=want_data)
+        if gp is not None and params is not None:
+            gp = gp.to(params.dtype)
+        if gd is not None:
+            gd = gd.to(data.dtype)
+        return gp, gd, None, None, None
+
+
+def expectation(plan: Plan, obs: Observable, params, data=None, batch: Optional[int] = None) -> torch.Tensor:
+    """Differentiable [batch, nobs] expectations."""
+    if batch is None:
+        batch = data.shape[0] if data is not None and data.dim() == 2 else (
+            params.shape[0] if params is not None and params.dim() == 2 else 1)
+    return ExpvalFunction.apply(params, data, plan, obs, batch)

@@ -1,0 +1,145 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/dq.h declares, and rejects bad arguments on the host with the
+documented status codes (no device work is reached by these calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dq.h")
+
+
+def _built():
+    from paper_2512_18995_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2512_18995_amd import build
+        build.build()
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _built()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dq_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_header_function(L):
+    names = header_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), "libdq.so does not export %s" % n
+    assert sorted(L.EXPORTS) == names
+
+
+def test_version(L):
+    assert L.lib().dq_version() == 1
+
+
+class G:
+    def __init__(self, op, wires, src="none", idx=-1, scale=1.0, matrix=None):
+        self.op, self.wires, self.src, self.idx, self.scale, self.matrix = op, tuple(wires), src, idx, scale, matrix
+
+
+def _create(L, n, gates, nparams=0, ndata=0, dtype=0, opt=None):
+    arr, keep = L.gate_array(gates)
+    h = ctypes.c_void_p()
+    st = L.lib().dq_plan_create(ctypes.byref(h), n, arr, len(gates), nparams, ndata, dtype,
+                                ctypes.byref(opt) if opt is not None else None)
+    return st, h
+
+
+@pytest.mark.parametrize("n,gates,np_,nd,code", [
+    (0, [], 0, 0, 4),                                         # nqubits out of range
+    (35, [], 0, 0, 4),
+    (3, [G("h", (3,))], 0, 0, 1),                             # wire out of range
+    (3, [G("cnot", (1, 1))], 0, 0, 1),                        # repeated wire
+    (3, [G("cnot", (1,))], 0, 0, 1),                          # wrong arity
+    (3, [G("ry", (0,), "param", 5)], 2, 0, 1),                # param index out of range
+    (3, [G("ry", (0,), "data", 0)], 2, 0, 1),                 # data index without data
+    (3, [G("h", (0,), "param", 0)], 2, 0, 1),                 # angle on a fixed gate
+    (3, [G("unitary", (0, 1))], 0, 0, 1),                     # unitary without matrix
+])
+def test_plan_create_rejects(L, n, gates, np_, nd, code):
+    st, h = _create(L, n, gates, np_, nd)
+    assert st == code, (st, L.lib().dq_last_error())
+    assert h.value is None
+    assert L.lib().dq_last_error().decode() != ""
+
+
+def test_plan_create_and_stats(L):
+    gates = [G("ry", (q,), "param", q) for q in range(10)] + [G("cnot", (q, (q + 1) % 10)) for q in range(10)]
+    st, h = _create(L, 10, gates, 10, 0)
+    assert st == 0, L.lib().dq_last_error()
+    assert L.lib().dq_last_error().decode() == ""
+    s = L.DqPlanStats()
+    assert L.lib().dq_plan_get_stats(h, ctypes.byref(s)) == 0
+    assert s.nqubits == 10 and s.ngates == 20 and s.grad_gates == 10
+    assert s.folded_gates == 10          # every leading RY folds into the first write
+    assert s.tile_bits == 4              # n - 6 register bits at n = 10
+    assert s.fwd_tile_passes == 1        # the whole register fits one wave tile
+    sz = ctypes.c_size_t(0)
+    assert L.lib().dq_workspace_size(h, None, 4, 1, 0, ctypes.byref(sz)) == 0 and sz.value > 0
+    assert L.lib().dq_workspace_size(h, None, 4, 1, 1, ctypes.byref(sz)) == 1   # adjoint needs an observable
+    assert L.lib().dq_workspace_size(h, None, 0, 0, 0, ctypes.byref(sz)) == 1   # batch >= 1
+    L.lib().dq_plan_destroy(h)
+
+
+def test_plain_path_has_one_step_per_gate(L):
+    gates = [G("h", (q,)) for q in range(8)] + [G("cz", (0, 1)), G("rzz", (2, 5), "none", -1, 0.3)]
+    st, h = _create(L, 8, gates, 0, 0, 0, L.DqOptions(0, 0, 1, 0))
+    assert st == 0
+    s = L.DqPlanStats()
+    L.lib().dq_plan_get_stats(h, ctypes.byref(s))
+    assert s.fwd_steps == 10 and s.fwd_tile_passes == 0 and s.folded_gates == 0
+    L.lib().dq_plan_destroy(h)
+
+
+def test_obs_create_validation(L):
+    terms, off = L.pauli_arrays(3, [[(1.0, "XZX")], [(0.5, "ZZI"), (2.0, "IIY")]])
+    h = ctypes.c_void_p()
+    assert L.lib().dq_obs_create(ctypes.byref(h), 3, terms, off, 2) == 0
+    L.lib().dq_obs_destroy(h)
+    bad = (L.DqPauliTerm * 1)()
+    bad[0].coef, bad[0].xmask, bad[0].zmask = 1.0, 1 << 3, 0          # wire 3 of a 3-qubit register
+    off1 = (ctypes.c_int64 * 2)(0, 1)
+    assert L.lib().dq_obs_create(ctypes.byref(h), 3, bad, off1, 1) == 1
+    off_bad = (ctypes.c_int64 * 2)(1, 0)
+    assert L.lib().dq_obs_create(ctypes.byref(h), 3, bad, off_bad, 1) == 1
+    with pytest.raises(ValueError):
+        L.pauli_arrays(3, [[(1.0, "XZ")]])
+
+
+def test_calls_validate_before_device_work(L):
+    gates = [G("ry", (q,), "param", q) for q in range(8)]
+    st, h = _create(L, 8, gates, 8, 0)
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    # NULL state
+    assert lib.dq_apply_circuit(h, None, 1, fake, 0, None, 0, 1, fake, 1 << 20, None) == 1
+    # params missing
+    assert lib.dq_apply_circuit(h, fake, 1, None, 0, None, 0, 1, fake, 1 << 20, None) == 1
+    # params stride shorter than a row
+    assert lib.dq_apply_circuit(h, fake, 2, fake, 3, None, 0, 1, fake, 1 << 20, None) == 1
+    # workspace too small
+    assert lib.dq_apply_circuit(h, fake, 1, fake, 0, None, 0, 1, fake, 16, None) == 3
+    assert "workspace" in lib.dq_last_error().decode()
+    # batch out of range
+    assert lib.dq_apply_circuit(h, fake, 0, fake, 0, None, 0, 1, fake, 1 << 20, None) == 1
+    assert lib.dq_apply_circuit(h, fake, 70000, fake, 0, None, 0, 1, fake, 1 << 40, None) == 4
+    # observable for another register size
+    terms, off = L.pauli_arrays(4, [[(1.0, "ZIII")]])
+    o = ctypes.c_void_p()
+    assert lib.dq_obs_create(ctypes.byref(o), 4, terms, off, 1) == 0
+    assert lib.dq_expval(h, o, fake, 1, fake, fake, 1 << 20, None) == 1
+    assert lib.dq_adjoint_grad(h, o, fake, 1, fake, 0, None, 0, fake, fake, None, 0, fake, 1 << 20, None) == 1
+    lib.dq_obs_destroy(o)
+    lib.dq_plan_destroy(h)

@@ -1,0 +1,202 @@
+"""HIP path vs the oracle, element by element, through the C ABI.
+
+Sizes are small enough for the oracle to finish in seconds and still span
+several register tiles (n >= 7 splits the register into 64-lane x 2^R
+tiles) with every wire position as lane bit and as register bit."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpu_helpers import DEV, RTOL, assert_state, gpu_forward, normwise, rand_state, t64
+
+import paper_2512_18995_amd as dq
+
+pytestmark = pytest.mark.gpu
+DTYPES = ["c64", "c128"]
+FUSION = [True, False]
+
+
+def _id(x):
+    return str(x)
+
+
+# ------------------------------------------------------------------ single gates
+ONE_Q = ["h", "x", "y", "z", "rx", "ry", "rz"]
+TWO_Q = ["cnot", "cz", "swap", "cp", "rzz"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fusion", FUSION, ids=["tile", "plain"])
+@pytest.mark.parametrize("n", [5, 9])
+def test_every_gate_every_wire(dtype, fusion, n):
+    """Each gate kind on every wire (one-qubit) / ordered wire pair
+    (two-qubit), applied to a random state."""
+    rng = np.random.default_rng(100 + n)
+    x = rand_state(rng, n)
+    for op in ONE_Q + TWO_Q:
+        if op in ONE_Q:
+            wire_sets = [(w,) for w in range(n)]
+        else:
+            wire_sets = [(a, b) for a in range(n) for b in range(n) if a != b]
+        for wires in wire_sets:
+            theta = float(rng.uniform(0, 2 * np.pi))
+            src = "param" if op in W.ROTATIONS else "none"
+            c = W.Circuit(n, [W.Gate(op, wires, src, 0 if src == "param" else -1)], 1 if src == "param" else 0)
+            params = np.array([theta]) if src == "param" else None
+            _, st = gpu_forward(c, params, None, 1, dtype, fusion, init=x)
+            want = oracle.state(c, params, None, psi0=x)
+            assert_state(st.cpu().numpy()[0], want, dtype, 1, "%s%s n=%d" % (op, wires, n))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fusion", FUSION, ids=["tile", "plain"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_dense_unitary(dtype, fusion, k):
+    rng = np.random.default_rng(200 + k)
+    n = 9
+    x = rand_state(rng, n)
+    for trial in range(6):
+        wires = tuple(int(w) for w in rng.choice(n, size=k, replace=False))
+        c = W.Circuit(n, [W.Gate("unitary", wires, matrix=W.random_unitary(rng, k))])
+        _, st = gpu_forward(c, None, None, 1, dtype, fusion, init=x)
+        assert_state(st.cpu().numpy()[0], oracle.state(c, psi0=x), dtype, 1, "unitary%s" % (wires,))
+
+
+# ------------------------------------------------------------------ random circuits
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fusion", FUSION, ids=["tile", "plain"])
+@pytest.mark.parametrize("n,batch,per_sample", [(3, 2, False), (7, 3, True), (10, 2, False), (12, 3, True)])
+def test_random_circuit_states_and_expvals(dtype, fusion, n, batch, per_sample):
+    rng = np.random.default_rng(300 + n)
+    c = W.random_circuit(rng, n, 12 * n, with_data=True, max_unitary_k=min(3, n))
+    params, data = W.random_params(rng, c, batch, per_sample)
+    obs = [W.random_pauli_sum(rng, n, 4), W.random_pauli_sum(rng, n, 3), [(1.0, "Z" + "I" * (n - 1))]]
+    plan, st = gpu_forward(c, params, data, batch, dtype, fusion)
+    got = st.cpu().numpy()
+    O = dq.Observable(n, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    for b in range(batch):
+        want = oracle.state(c, params, data, b)
+        assert_state(got[b], want, dtype, len(c.gates), "sample %d" % b)
+        normwise(E[b], oracle.expvals(n, want, obs), RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12,
+                 "expval sample %d" % b)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_fold_init_matches_unfolded(dtype):
+    rng = np.random.default_rng(7)
+    n = 11
+    gates = [W.Gate("rx", (q,), "data", q) for q in range(n)] + [W.Gate("h", (0,)), W.Gate("ry", (3,), "param", 0)]
+    gates += W.hea_layers(n, 2, ("ry", "rz"), "ring", first_param=1)[0]
+    c = W.Circuit(n, gates, 1 + 4 * n, n)
+    params, data = W.random_params(rng, c, 3)
+    a = gpu_forward(c, params, data, 3, dtype, True, fold=True)[1].cpu().numpy()
+    b = gpu_forward(c, params, data, 3, dtype, True, fold=False)[1].cpu().numpy()
+    for s in range(3):
+        want = oracle.state(c, params, data, s)
+        assert_state(a[s], want, dtype, len(gates), "folded")
+        assert_state(b[s], want, dtype, len(gates), "unfolded")
+
+
+# ------------------------------------------------------------------ adjoint gradients
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fusion", FUSION, ids=["tile", "plain"])
+@pytest.mark.parametrize("n,batch,per_sample", [(4, 2, False), (8, 2, True), (11, 3, False)])
+def test_adjoint_vs_parameter_shift(dtype, fusion, n, batch, per_sample):
+    rng = np.random.default_rng(400 + n)
+    ops = ("h", "x", "rx", "ry", "rz", "cnot", "cz", "swap", "cp", "rzz", "unitary")
+    c = W.random_circuit(rng, n, 8 * n, ops=ops, with_data=True, max_unitary_k=2)
+    params, data = W.random_params(rng, c, batch, per_sample)
+    obs = [W.random_pauli_sum(rng, n, 5), W.random_pauli_sum(rng, n, 2)]
+    w = rng.standard_normal((batch, len(obs)))
+    plan, st = gpu_forward(c, params, data, batch, dtype, fusion)
+    O = dq.Observable(n, obs)
+    gp, gd = dq.adjoint_grad(plan, O, st, t64(params), t64(data), t64(w))
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w, batch, threads=8)
+    normwise(gp.cpu().numpy(), rp, RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12, "d/dparams")
+    normwise(gd.cpu().numpy(), rd, RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12, "d/ddata")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_autograd_function(dtype):
+    rng = np.random.default_rng(11)
+    n, B = 9, 4
+    c = W.random_circuit(rng, n, 60, ops=("h", "rx", "ry", "rz", "cnot", "cz"), with_data=True)
+    params, data = W.random_params(rng, c, B)
+    obs = [W.tfim_open(n, 0.5)]
+    plan, O = dq.Plan(c, dtype), dq.Observable(n, obs)
+    p = torch.tensor(params, device=DEV, requires_grad=True)
+    d = torch.tensor(data, device=DEV, requires_grad=True)
+    E = dq.expectation(plan, O, p, d)
+    w = torch.tensor(rng.standard_normal((B, 1)), device=DEV)
+    (E * w).sum().backward()
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w.cpu().numpy(), B, threads=8)
+    normwise(p.grad.cpu().numpy(), rp, RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12, "autograd params")
+    normwise(d.grad.cpu().numpy(), rd, RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12, "autograd data")
+
+
+# ------------------------------------------------------------------ paper examples
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fusion", FUSION, ids=["tile", "plain"])
+def test_listing1_printed_values(dtype, fusion):
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "listing1.json")))
+    c, th, data, obs = W.listing1(g["theta"], g["data"])
+    plan, st = gpu_forward(c, th, data, 1, dtype, fusion)
+    O = dq.Observable(3, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    assert abs(E[0, 0] - g["expval"]) <= g["tol"]
+    gp, _ = dq.adjoint_grad(plan, O, st, t64(th), t64(data), t64(np.ones((1, 1))))
+    assert np.max(np.abs(gp.cpu().numpy() - g["grad"])) <= g["tol"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [4, 10, 13])
+def test_qft_is_dft(dtype, n):
+    rng = np.random.default_rng(500 + n)
+    x = rand_state(rng, n)
+    c = W.qft(n)
+    _, st = gpu_forward(c, None, None, 1, dtype, True, init=x)
+    assert_state(st.cpu().numpy()[0], np.fft.ifft(x, norm="ortho"), dtype, len(c.gates), "QFT")
+
+
+def test_dist_listing_data_gradient():
+    c, params, data, obs = W.dist_listing()
+    plan, st = gpu_forward(c, params, data, 1, "c128", True)
+    O = dq.Observable(4, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    normwise(E[0], oracle.forward(c, params, data, obs, 1)[0], 1e-12, 1e-14, "expvals")
+    _, gd = dq.adjoint_grad(plan, O, st, None, t64(data), t64(np.ones((1, 2))))
+    _, rd = oracle.grad_param_shift(c, params, data, obs, np.ones((1, 2)), 1)
+    normwise(gd.cpu().numpy(), rd, 1e-11, 1e-13, "data gradient")
+
+
+# ------------------------------------------------------------------ properties
+def test_deterministic_bitwise():
+    rng = np.random.default_rng(13)
+    n, B = 14, 4
+    c = W.random_circuit(rng, n, 80, ops=("h", "rx", "ry", "rz", "cnot", "cz", "rzz"))
+    params, _ = W.random_params(rng, c, B, True)
+    obs = [W.random_pauli_sum(rng, n, 6)]
+    O = dq.Observable(n, obs)
+    outs = []
+    for _ in range(2):
+        plan, st = gpu_forward(c, params, None, B, "c64", True)
+        E = dq.expval(plan, O, st)
+        gp, _ = dq.adjoint_grad(plan, O, st, t64(params), None, t64(np.ones((B, 1))))
+        outs.append((E.cpu().numpy(), gp.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_norm_preserved_deep_c64():
+    rng = np.random.default_rng(17)
+    n, B = 16, 2
+    c = W.random_circuit(rng, n, 600, ops=("h", "rx", "ry", "rz", "cnot", "cz", "rzz", "cp", "swap"))
+    params, _ = W.random_params(rng, c, B)
+    _, st = gpu_forward(c, params, None, B, "c64", True)
+    norms = torch.linalg.vector_norm(st.to(torch.complex128), dim=1).cpu().numpy()
+    assert np.all(np.abs(norms - 1) < 1e-5), norms

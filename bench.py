@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched state-vector hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg5]
+
+One step = one pass of the whole hot path over one batch of synthetic input:
+product-state initialisation with the leading one-qubit layer folded in,
+the forward gate sweeps (register-tile passes), the Pauli-sum expectation,
+and the adjoint gradient (lambda seed, reverse tile sweeps over (psi,
+lambda), deterministic gradient reduction).  The default workload is the
+32-qubit complex64 hardware-efficient ansatz (20 layers of RY, RZ on every
+wire plus a CNOT ring, 1280 parameters, observable sum_i Z_i Z_{i+1} open
+chain, seed 1005): a 34.4 GB state, fwd + adjoint gradient.
+
+Printed: one JSON line with the throughput (circuits/s, forward + all
+gradients), the roofline of the dominant kernel measured with hipEvents
+around every launch of the timed steps, the oracle timed on the host on a
+bounded sample, and the plain path (one launch per gate, central finite
+differences) measured on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+METRIC = "HBM GB/s per gate sweep; fwd+adjoint-grad circuits/sec vs plain path"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "runtime.cpp", "dq_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2512_18995_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, kernel):
+    """HBM traffic per launch from the committed rocprofv3 --pmc summary, or
+    None when there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    if doc.get("source_hash") != kernel_source_hash():
+        return None
+    return doc.get("bytes_per_launch")
+
+
+def cpu_baseline(wl_id, full):
+    """The oracle (single thread) on a bounded sample of the workload family,
+    scaled to circuits/s of the full workload with parameter-shift gradients."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    oracle.lib()
+    if wl_id == "cfg5":
+        n_s = 20
+        wl = W.config(5, n=n_s)
+    elif wl_id == "cfg3":
+        n_s = 16
+        wl = W.config(3, n=n_s, batch=1)
+    elif wl_id == "cfg2":
+        n_s = 16
+        wl = W.config(2, batch=1)
+    else:
+        n_s = full.circuit.n
+        wl = W.config(1)
+    c = wl.circuit
+    t0 = time.perf_counter()
+    oracle.forward(c, wl.params, wl.data, wl.observables, 1, threads=1, samples=[0])
+    t = time.perf_counter() - t0
+    G_full, G_s = len(full.circuit.gates), len(c.gates)
+    t_fwd_full = t * (2.0 ** (full.circuit.n - n_s)) * (G_full / G_s)
+    evals = (2 * full.circuit.n_params + 1) if full.grad else 1       # parameter shift: 2 runs per parameter
+    per_circuit = t_fwd_full * evals
+    return {"value": 1.0 / per_circuit, "unit": "circuits/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle forward + expectation of the same circuit family at n=%d (%d gates, 1 sample) took "
+                      "%.2f s on one host thread; scaled by 2^%d amplitudes x %d/%d gates x %d evaluations "
+                      "(parameter shift, 2 per parameter + 1) per fwd+grad circuit" % (
+                          n_s, G_s, t, full.circuit.n - n_s, G_full, G_s, evals),
+            "sample_seconds": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg5", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--tile-bits", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-layers", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device copy first (reference for rocprofv3 byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (the state-vector path on one MI355X); "
+              "--gpus %d / WORLD_SIZE=%d is not supported" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2512_18995_amd as dq
+    import workloads as W
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    cid = int(args.workload[3:])
+    wl = W.config(cid)
+    c = wl.circuit
+    B = wl.batch
+    plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits)
+    obs = dq.Observable(c.n, wl.observables)
+    params = torch.as_tensor(wl.params, dtype=torch.float64, device=dev)
+    data = None if wl.data is None else torch.as_tensor(wl.data, dtype=torch.float64, device=dev)
+    per_sample = wl.params.ndim == 2 or data is not None
+    grad = wl.grad
+    state = plan.state(B, dev)
+    ws = plan.workspace(B, per_sample, 1 if grad else 0, obs, dev)
+    gout = torch.ones((B, 1), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        dq.apply_circuit(plan, state, params, data, from_zero=True, ws=ws)
+        E = dq.expval(plan, obs, state, ws=ws)
+        gp = None
+        if grad:
+            gp, _ = dq.adjoint_grad(plan, obs, state, params, data, gout, ws=ws, want_data=False)
+        return E, gp
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile_enable(True)
+    plan.profile_read(reset=True)
+    torch.cuda.synchronize()                                    # barrier is trivial at one rank
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E, gp = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = plan.profile_read(reset=True)
+    plan.profile_enable(False)
+    ms_per_step = dt * 1000.0 / args.steps
+    value = B * args.steps / dt
+
+    kernels = {}
+    for k, v in prof.items():
+        if v["launches"]:
+            kernels[k] = {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms"] / args.steps,
+                          "avg_launch_ms": v["ms"] / v["launches"],
+                          "GBps": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["bytes"] and v["ms"] else None}
+    dom = max((k for k in prof if prof[k]["launches"]), key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    bytes_per_launch = d["bytes"] / d["launches"]
+    achieved = (bytes_per_launch / 1e9) / (d["ms"] / d["launches"] / 1e3)
+    traffic = load_traffic(args.workload, dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "avg_launch_ms": d["ms"] / d["launches"]}
+
+    # sanity of the timed result (outside the timed region)
+    Ev = float(E[0, 0].item())
+    checks = {"E_sample0": Ev, "sum_abs_coef": float(sum(abs(cf) for cf, _ in wl.observables[0]))}
+    if gp is not None:
+        checks["grad_norm"] = float(torch.linalg.vector_norm(gp).item())
+    dq.apply_circuit(plan, state, params, data, from_zero=True, ws=ws)
+    nrm = torch.linalg.vector_norm(state[0]).item()
+    checks["norm_err_sample0"] = abs(nrm - 1.0)
+    st = plan.stats()
+
+    # plain path: one launch per gate, gradients by central differences
+    plain = None
+    if not args.no_plain:
+        Lp = min(args.plain_layers, 2)
+        per_layer = len(c.gates) // max(1, {"cfg1": 4, "cfg2": 8, "cfg3": 12, "cfg5": 20}[args.workload])
+        sub = W.Circuit(c.n, c.gates[:per_layer * Lp], c.n_params, c.n_data)
+        pplan = dq.Plan(sub, wl.dtype, fusion=False)
+        pws = pplan.workspace(B, per_sample, 0, None, dev)
+        dq.apply_circuit(pplan, state, params, data, from_zero=True, ws=pws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dq.apply_circuit(pplan, state, params, data, from_zero=True, ws=pws)
+        torch.cuda.synchronize()
+        t_sub = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        dq.expval(plan, obs, state, ws=ws)
+        torch.cuda.synchronize()
+        t_exp = time.perf_counter() - t2
+        t_fwd = t_sub * len(c.gates) / len(sub.gates) + t_exp
+        evals = (2 * c.n_params + 1) if grad else 1
+        plain = {"value": B / (t_fwd * evals), "unit": "circuits/s",
+                 "sample": "plain path (one kernel launch per gate, no fusion) timed on the first %d gates of the "
+                           "workload at full size (%.3f s) plus one expectation (%.3f s), scaled to %d gates and "
+                           "to %d forward evaluations (central finite differences: 2 per parameter + 1)" % (
+                               len(sub.gates), t_sub, t_exp, len(c.gates), evals),
+                 "fwd_seconds_est": t_fwd}
+        del pplan, pws
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, wl)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "circuits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "qubits": c.n, "batch": B, "gates": len(c.gates), "params": c.n_params,
+                   "grad": "adjoint" if grad else "none", "observable_terms": len(wl.observables[0]),
+                   "seed": wl.seed, "parallelism": "none (one GPU)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain_path": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "kernels": kernels,
+        "plan": {"fwd_tile_passes": st["fwd_tile_passes"], "adj_steps": st["adj_steps"],
+                 "folded_gates": st["folded_gates"], "tile_bits": st["tile_bits"]},
+        "checks": checks,
+        "source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

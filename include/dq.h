@@ -155,8 +155,8 @@ dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms
 void dq_obs_destroy(dq_obs obs);
 
 /* Workspace bytes needed by dq_apply_circuit / dq_expval (grad = 0) or
- * dq_adjoint_grad (grad = 1) for this batch; per_sample = 1 when params or
- * data differ per sample.  obs may be NULL when grad = 0 and no expval is
+ * dq_adjoint_grad (grad = 1; grad = 2 with preserve_state = 1) for this
+ * batch; per_sample = 1 when params or data differ per sample.  obs may be NULL when grad = 0 and no expval is
  * taken.  The workspace is a caller-owned device buffer, 256-byte aligned. */
 dq_status dq_workspace_size(dq_plan plan, dq_obs obs, int64_t batch, int32_t per_sample,
                             int32_t grad, size_t *bytes);
@@ -194,6 +194,34 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch,
                           int64_t data_bstride, const double *grad_out, double *grad_params,
                           double *grad_data, int32_t preserve_state, void *ws, size_t ws_bytes,
                           void *stream);
+
+/* Kernel timing for benchmarks.  While enabled on a plan, every kernel
+ * launch made for it (apply, expval, adjoint) is bracketed by a pair of
+ * hipEvents recorded on the launch's stream.  dq_profile_read waits for the
+ * recorded events and returns, per kernel family, the number of launches,
+ * the summed event time and the summed algorithmic bytes (what the launch
+ * must read plus write: 2 states for a forward sweep, 4 for an adjoint
+ * sweep, half / a quarter of a state for CNOT / CZ, ...).  reset = 1
+ * clears the counters.  Events are created on first need and kept by the
+ * plan; profiling adds two event records per launch and nothing else. */
+enum {
+    DQ_PROF_FWD_TILE = 0,   /* register-tile forward pass */
+    DQ_PROF_ADJ_TILE = 1,   /* register-tile adjoint pass over (psi, lambda) */
+    DQ_PROF_GATE = 2,       /* one-gate sweep of the plain path */
+    DQ_PROF_GRAD_GATE = 3,  /* one-gate gradient reduction of the plain adjoint */
+    DQ_PROF_EXPVAL = 4,     /* Pauli-sum expectation reduction */
+    DQ_PROF_LAMBDA = 5,     /* adjoint seed lambda = sum w H psi */
+    DQ_PROF_INIT = 6,       /* state initialisation / product-state write */
+    DQ_PROF_OTHER = 7,      /* matrix preparation, final gradient reduction, copies */
+    DQ_PROF_KINDS = 8
+};
+typedef struct {
+    int64_t launches[DQ_PROF_KINDS];
+    double ms[DQ_PROF_KINDS];
+    double bytes[DQ_PROF_KINDS];
+} dq_profile;
+dq_status dq_profile_enable(dq_plan plan, int32_t on);
+dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset);
 
 /* Description of the last error on this thread ("" after success). */
 const char *dq_last_error(void);

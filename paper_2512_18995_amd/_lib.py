@@ -22,7 +22,8 @@ C64, C128 = 0, 1
 
 EXPORTS = ["dq_plan_create", "dq_plan_destroy", "dq_plan_get_stats", "dq_obs_create", "dq_obs_destroy",
            "dq_workspace_size", "dq_state_init", "dq_apply_circuit", "dq_expval", "dq_adjoint_grad",
-           "dq_last_error", "dq_version"]
+           "dq_last_error", "dq_version", "dq_profile_enable", "dq_profile_read"]
+PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other"]
 
 
 class DqGate(ctypes.Structure):
@@ -42,6 +43,10 @@ class DqPlanStats(ctypes.Structure):
     _fields_ = [("nqubits", c_int32), ("dtype", c_int32), ("ngates", c_int64), ("fwd_steps", c_int64),
                 ("fwd_tile_passes", c_int64), ("fwd_dense_blocks", c_int64), ("adj_steps", c_int64),
                 ("folded_gates", c_int64), ("grad_gates", c_int64), ("tile_bits", c_int32)]
+
+
+class DqProfile(ctypes.Structure):
+    _fields_ = [("launches", c_int64 * 8), ("ms", c_double * 8), ("bytes", c_double * 8)]
 
 
 class DqError(RuntimeError):
@@ -75,10 +80,12 @@ def lib():
         L.dq_expval.argtypes = [vp, vp, vp, c_int64, vp, vp, c_size_t, vp]
         L.dq_adjoint_grad.argtypes = [vp, vp, vp, c_int64, vp, c_int64, vp, c_int64, vp, vp, vp, c_int32, vp,
                                       c_size_t, vp]
+        L.dq_profile_enable.argtypes = [vp, c_int32]
+        L.dq_profile_read.argtypes = [vp, POINTER(DqProfile), c_int32]
         L.dq_last_error.restype = c_char_p
         L.dq_version.restype = c_int32
         for f in ("dq_plan_create", "dq_plan_get_stats", "dq_obs_create", "dq_workspace_size", "dq_state_init",
-                  "dq_apply_circuit", "dq_expval", "dq_adjoint_grad"):
+                  "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib

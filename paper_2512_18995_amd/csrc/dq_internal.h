@@ -117,6 +117,8 @@ hipError_t launch_gatek(int dbl, void *st, int32_t n, int64_t batch, int32_t k, 
                         const void *mats, int64_t mstride, int64_t off, hipStream_t s);
 hipError_t launch_tile_fwd(int dbl, const TileArgs &a, hipStream_t s);
 hipError_t launch_tile_adj(int dbl, const TileArgs &a, hipStream_t s);
+// resident single-wave workgroups of the adjoint tile kernel on the current device
+int tile_adj_capacity(int dbl, int R);
 hipError_t launch_grad_gate(int dbl, const void *psi, const void *lam, int32_t n, int64_t batch, int32_t gen,
                             int32_t bit0, int32_t bit1, double *partial, int32_t wps, int32_t ngrad,
                             int32_t gslot, hipStream_t s);

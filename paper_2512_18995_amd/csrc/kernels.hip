@@ -882,24 +882,54 @@ hipError_t launch_gatek(int dbl, void *st, int32_t n, int64_t batch, int32_t k, 
     DQ_LAUNCH_RET;
 }
 
-static unsigned tile_grid(int64_t tiles) {
-    // enough resident waves to keep every CU's memory pipes busy; each wave
-    // walks a strided subset of the tiles
-    const int64_t cap = 256 * 16;
+// Resident single-wave workgroups of a tile kernel on the current device
+// (occupancy x compute units), cached per device and instantiation.
+template <typename K>
+static int resident_waves(K kernel, size_t lds, int key) {
+    static int cache[64][32];
+    static bool init = false;
+    if (!init) {
+        for (auto &r : cache)
+            for (int &c : r) c = 0;
+        init = true;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev >= 64) dev = 0;
+    int &c = cache[dev][key & 31];
+    if (c == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, lds) != hipSuccess || per_cu < 1)
+            per_cu = 2;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        c = per_cu * cus;
+    }
+    return c;
+}
+
+static unsigned tile_grid(int64_t tiles, int resident) {
+    // one resident wave per slot; each wave walks a strided subset of the tiles
+    const int64_t cap = resident > 0 ? resident : 4096;
     return (unsigned)(tiles < cap ? (tiles < 1 ? 1 : tiles) : cap);
+}
+
+template <typename T, int R>
+static void tile_fwd_r(const TileArgs &a, hipStream_t s) {
+    const int key = (sizeof(T) == 8 ? 16 : 0) + R;
+    const unsigned g = tile_grid(a.batch << (a.n - 6 - R), resident_waves(k_tile_fwd<T, R>, 0, key));
+    hipLaunchKernelGGL((k_tile_fwd<T, R>), dim3(g), dim3(64), 0, s, a);
 }
 
 template <typename T>
 static void tile_fwd_t(const TileArgs &a, hipStream_t s) {
-    const unsigned g = tile_grid(a.batch << (a.n - 6 - a.R));
     switch (a.R) {
-    case 1: hipLaunchKernelGGL((k_tile_fwd<T, 1>), dim3(g), dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tile_fwd<T, 2>), dim3(g), dim3(64), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_tile_fwd<T, 3>), dim3(g), dim3(64), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_tile_fwd<T, 4>), dim3(g), dim3(64), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_tile_fwd<T, 5>), dim3(g), dim3(64), 0, s, a); break;
+    case 1: tile_fwd_r<T, 1>(a, s); break;
+    case 2: tile_fwd_r<T, 2>(a, s); break;
+    case 3: tile_fwd_r<T, 3>(a, s); break;
+    case 4: tile_fwd_r<T, 4>(a, s); break;
+    case 5: tile_fwd_r<T, 5>(a, s); break;
     default:
-        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_tile_fwd<T, 6>), dim3(g), dim3(64), 0, s, a);
+        if constexpr (sizeof(T) == 4) tile_fwd_r<T, 6>(a, s);
         break;
     }
 }
@@ -926,6 +956,26 @@ static void tile_adj_t(const TileArgs &a, hipStream_t s) {
     default:
         if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_tile_adj<T, 5>), g, dim3(64), lds, s, a);
         break;
+    }
+}
+
+int tile_adj_capacity(int dbl, int R) {
+    const size_t lds = sizeof(double) * 64 * 32;     // the most accumulator slots a pass may use
+    const int key = 8 + (dbl ? 16 : 0) + R;
+    if (dbl) {
+        switch (R) {
+        case 1: return resident_waves(k_tile_adj<double, 1>, lds, key);
+        case 2: return resident_waves(k_tile_adj<double, 2>, lds, key);
+        case 3: return resident_waves(k_tile_adj<double, 3>, lds, key);
+        default: return resident_waves(k_tile_adj<double, 4>, lds, key);
+        }
+    }
+    switch (R) {
+    case 1: return resident_waves(k_tile_adj<float, 1>, lds, key);
+    case 2: return resident_waves(k_tile_adj<float, 2>, lds, key);
+    case 3: return resident_waves(k_tile_adj<float, 3>, lds, key);
+    case 4: return resident_waves(k_tile_adj<float, 4>, lds, key);
+    default: return resident_waves(k_tile_adj<float, 5>, lds, key);
     }
 }
 

@@ -62,6 +62,36 @@ int gen_of(int op) {
 }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+}  // namespace
+struct dq_plan_s;
+namespace {
+hipEvent_t prof_event(dq_plan_s &p);
+void prof_push(dq_plan_s &p, int kind, int nl, hipEvent_t a, hipEvent_t b, double bytes);
+bool prof_on(const dq_plan_s &p);
+
+// Brackets one or more launches with a pair of events when profiling is on.
+struct ProfScope {
+    dq_plan_s &p;
+    int kind, nl;
+    double bytes;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(dq_plan_s &pl, int k, int nlaunch, double b, hipStream_t st) : p(pl), kind(k), nl(nlaunch), bytes(b), s(st) {
+        if (prof_on(p)) {
+            a = prof_event(p);
+            (void)hipEventRecord(a, s);
+        }
+    }
+    void done() {
+        if (a) {
+            hipEvent_t b = prof_event(p);
+            (void)hipEventRecord(b, s);
+            prof_push(p, kind, nl, a, b, bytes);
+            a = nullptr;
+        }
+    }
+};
+
 // ================================================================ plan
 enum StepKind { ST_TILE = 0, ST_G1, ST_CNOT, ST_CZ, ST_GK, ST_GRAD };
 
@@ -120,6 +150,18 @@ struct dq_plan_s {
     std::vector<double> pf, df;
     std::mutex mu;
     std::map<int, DevData> dev;
+    // kernel timing (dq_profile_enable / dq_profile_read)
+    bool prof = false;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    struct PRec {
+        int kind;
+        int nl;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<PRec> precs;
+    dq_profile acc{};
 };
 
 struct dq_obs_s {
@@ -133,6 +175,20 @@ struct dq_obs_s {
 };
 
 namespace {
+
+bool prof_on(const dq_plan_s &p) { return p.prof; }
+hipEvent_t prof_event(dq_plan_s &p) {
+    if (p.evused < p.evpool.size()) return p.evpool[p.evused++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p.evpool.push_back(e);
+    p.evused++;
+    return e;
+}
+void prof_push(dq_plan_s &p, int kind, int nl, hipEvent_t a, hipEvent_t b, double bytes) {
+    if (a && b) p.precs.push_back({kind, nl, a, b, bytes});
+}
+double state_bytes(const dq_plan_s &p, int64_t batch) { return (double)batch * std::ldexp(1.0, p.n) * (p.dbl ? 16 : 8); }
 
 // ---------------------------------------------------------------- slots
 int64_t add_slot(dq_plan_s &p, int dim, const std::vector<int> &factors, int dagger) {
@@ -558,8 +614,20 @@ WsLayout layout(const dq_plan_s &p, const dq_obs_s *o, int64_t batch, int per_sa
 // ---------------------------------------------------------------- execution
 dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, void *lam, int64_t batch,
                       const void *mats, int64_t mstride, double *partial, int wps, hipStream_t s) {
+    const double SB = state_bytes(p, batch);
     for (const Step &S : prog.steps) {
         hipError_t e = hipSuccess;
+        const int nst = lam ? 2 : 1;   // states a per-gate sweep touches
+        double bytes = 0;
+        int kind = DQ_PROF_GATE, nl = nst;
+        switch (S.kind) {
+        case ST_TILE: kind = lam ? DQ_PROF_ADJ_TILE : DQ_PROF_FWD_TILE; nl = 1; bytes = (lam ? 4 : 2) * SB; break;
+        case ST_GRAD: kind = DQ_PROF_GRAD_GATE; nl = 1; bytes = 2 * SB; break;
+        case ST_CNOT: bytes = nst * SB; break;
+        case ST_CZ: bytes = nst * SB / 2; break;
+        default: bytes = nst * 2 * SB; break;
+        }
+        ProfScope ps(p, kind, nl, bytes, s);
         switch (S.kind) {
         case ST_TILE: {
             TileArgs a{};
@@ -597,6 +665,7 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
             }
             break;
         }
+        ps.done();
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
     }
     return DQ_OK;
@@ -716,6 +785,7 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
 
 void dq_plan_destroy(dq_plan plan) {
     if (!plan) return;
+    for (hipEvent_t e : plan->evpool) (void)hipEventDestroy(e);
     for (auto &kv : plan->dev) {
         int cur = 0;
         if (hipGetDevice(&cur) == hipSuccess) {
@@ -847,12 +917,18 @@ dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const doubl
     const int64_t mstride = per_sample ? plan->block : 0;
     char *w = (char *)ws;
     void *mats = w + L.mats;
+    ProfScope pp(*plan, DQ_PROF_OTHER, 1, 0.0, s);
     hipError_t e = launch_prepare(plan->dbl, d->gates, d->fixed, d->slots + prog.slot_lo,
                                   (int32_t)(prog.slot_hi - prog.slot_lo), params, params_bstride, data, data_bstride,
                                   mats, plan->block, bm, s);
+    pp.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
-    if (fold) e = launch_init_product(plan->dbl, state, plan->n, batch, mats, mstride, d->fold, s);
-    else if (from_zero) e = launch_init_zero(plan->dbl, state, plan->n, batch, s);
+    if (from_zero) {
+        ProfScope pi(*plan, DQ_PROF_INIT, 1, state_bytes(*plan, batch), s);
+        if (fold) e = launch_init_product(plan->dbl, state, plan->n, batch, mats, mstride, d->fold, s);
+        else e = launch_init_zero(plan->dbl, state, plan->n, batch, s);
+        pi.done();
+    }
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "init: %s", hipGetErrorString(e));
     if ((st = run_program(*plan, *d, prog, state, nullptr, batch, mats, mstride, nullptr, 0, s)) != DQ_OK) return st;
     return ok();
@@ -871,9 +947,11 @@ dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, 
     const DTerm *t = nullptr;
     if ((st = ensure_obs(*obs, &g, &t)) != DQ_OK) return st;
     const int eb = (int)expval_blocks(plan->n, batch);
+    ProfScope pe(*plan, DQ_PROF_EXPVAL, 2, state_bytes(*plan, batch) * (double)obs->groups.size(), (hipStream_t)stream);
     hipError_t e = launch_expval(plan->dbl, state, plan->n, batch, g, (int32_t)obs->groups.size(), t,
                                  (int32_t)obs->terms.size(), obs->nobs, (double *)((char *)ws + L.expv), eb, out,
                                  (hipStream_t)stream);
+    pe.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "expval: %s", hipGetErrorString(e));
     return ok();
 }
@@ -905,21 +983,36 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, 
     double *partial = (double *)(w + L.part);
     const int64_t bm = per_sample ? batch : 1;
     const int64_t mstride = per_sample ? plan->block : 0;
-    const int wps = (int)grad_waves(*plan, batch);
+    // partial sums per sample: at most grad_waves (the workspace size), and
+    // no more than the adjoint tile kernel keeps resident, so that one
+    // round of waves covers every tile
+    int wps = (int)grad_waves(*plan, batch);
+    if (plan->R_adj > 0) {
+        const int cap = std::max<int64_t>(1, tile_adj_capacity(plan->dbl, plan->R_adj) / batch);
+        wps = std::min(wps, cap);
+    }
     void *psi = state;
     hipError_t e;
+    const double SB = state_bytes(*plan, batch);
     if (preserve_state) {
         psi = w + L.keep;
+        ProfScope pc(*plan, DQ_PROF_OTHER, 1, 2 * SB, s);
         e = launch_copy(plan->dbl, psi, state, batch << plan->n, s);
+        pc.done();
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "copy: %s", hipGetErrorString(e));
     }
+    ProfScope pp(*plan, DQ_PROF_OTHER, 1, 0.0, s);
     e = launch_prepare(plan->dbl, d->gates, d->fixed, d->slots + plan->adj.slot_lo,
                        (int32_t)(plan->adj.slot_hi - plan->adj.slot_lo), params, params_bstride, data, data_bstride,
                        mats, plan->block, bm, s);
+    pp.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
+    ProfScope pl(*plan, DQ_PROF_LAMBDA, 1, 2 * SB, s);
     e = launch_lambda(plan->dbl, psi, lam, plan->n, batch, g, (int32_t)obs->groups.size(), t, grad_out, obs->nobs, s);
+    pl.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "lambda: %s", hipGetErrorString(e));
     if ((st = run_program(*plan, *d, plan->adj, psi, lam, batch, mats, mstride, partial, wps, s)) != DQ_OK) return st;
+    ProfScope pf(*plan, DQ_PROF_OTHER, 1, 0.0, s);
     if (plan->nparams > 0) {
         e = launch_grad_final(partial, batch, wps, plan->ngrad, d->poff, d->pg, d->pf, plan->nparams,
                               params_bstride != 0 ? 1 : 0, grad_params, s);
@@ -930,6 +1023,30 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, 
                               data_bstride != 0 ? 1 : 0, grad_data, s);
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "grad reduce: %s", hipGetErrorString(e));
     }
+    pf.done();
+    return ok();
+}
+
+dq_status dq_profile_enable(dq_plan plan, int32_t on) {
+    if (!plan) return fail(DQ_ERR_INVALID_ARG, "NULL plan");
+    plan->prof = on != 0;
+    return ok();
+}
+
+dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset) {
+    if (!plan || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    for (const auto &r : plan->precs) {
+        DQ_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        DQ_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        plan->acc.launches[r.kind] += r.nl;
+        plan->acc.ms[r.kind] += ms;
+        plan->acc.bytes[r.kind] += r.bytes;
+    }
+    plan->precs.clear();
+    plan->evused = 0;
+    *out = plan->acc;
+    if (reset) plan->acc = dq_profile{};
     return ok();
 }
 

@@ -62,6 +62,17 @@ class Plan:
         check(lib().dq_plan_get_stats(self._h, ctypes.byref(s)), "dq_plan_get_stats")
         return {k: getattr(s, k) for k, _ in _lib.DqPlanStats._fields_}
 
+    def profile_enable(self, on: bool = True):
+        """Bracket every kernel launch of this plan with hipEvents."""
+        check(lib().dq_profile_enable(self._h, 1 if on else 0), "dq_profile_enable")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{family: {"launches", "ms", "bytes"}} summed since the last reset."""
+        p = _lib.DqProfile()
+        check(lib().dq_profile_read(self._h, ctypes.byref(p), 1 if reset else 0), "dq_profile_read")
+        return {k: {"launches": p.launches[i], "ms": p.ms[i], "bytes": p.bytes[i]}
+                for i, k in enumerate(_lib.PROF_KINDS)}
+
     def workspace_size(self, batch: int, per_sample: bool = False, grad: int = 0, obs: "Observable" = None) -> int:
         n = ctypes.c_size_t(0)
         check(lib().dq_workspace_size(self._h, obs.handle if obs else None, batch, 1 if per_sample else 0, grad,

@@ -29,6 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+# fp32 vector FMA issue rate without packed-FP32 instructions (this build disables
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (the published 157.3
+# TFLOP/s counts packed v_pk_fma_f32); fp64 vector: 78.6 TFLOP/s
+ALU_PEAK_TFLOPS = {"c64": 78.6, "c128": 78.6}
 METRIC = "HBM GB/s per gate sweep; fwd+adjoint-grad circuits/sec vs plain path"
 
 
@@ -86,6 +90,79 @@ def cpu_baseline(wl_id, full):
             "sample_seconds": t}
 
 
+def sweeps(args):
+    """Single-gate sweep bandwidth: one kernel launch applies one gate to a
+    whole 2^n state (the plain path's kernels) or one op through a register
+    tile; GB/s = algorithmic bytes (every amplitude the gate touches, read and
+    written) / hipEvent time, averaged over repeats."""
+    import numpy as np
+    import torch
+    import paper_2512_18995_amd as dq
+    from paper_2512_18995_amd import engine
+    import workloads as W
+    dev = "cuda:0"
+    rows = []
+    for dtype, n in (("c64", args.sweep_qubits), ("c128", args.sweep_qubits - 1)):
+        st = torch.zeros((1, 1 << n), dtype=engine.CDTYPE[dtype], device=dev)
+        st[0, 0] = 1
+        cases = []
+        for w in (0, n - 30 + 10 if n >= 30 else 1, n // 2, n - 7, n - 4, n - 1):
+            cases.append(("h", (w,)))
+        cases += [("ry", (n // 2,)), ("rz", (n // 2,)), ("cnot", (0, n - 1)), ("cnot", (n - 1, 0)), ("cz", (1, n - 2)),
+                  ("rzz", (2, n - 3)), ("swap", (3, n - 5))]
+        rng = np.random.default_rng(0)
+        for k in (3, 4, 5):
+            cases.append(("unitary", tuple(range(n - k, n))))
+            cases.append(("unitary", tuple(range(0, k))))
+        for fusion in (False, True):
+            for op, wires in cases:
+                if fusion and op == "unitary":
+                    continue
+                src = "param" if op in W.ROTATIONS else "none"
+                g = W.Gate(op, wires, src, 0 if src == "param" else -1,
+                           matrix=W.random_unitary(rng, len(wires)) if op == "unitary" else None)
+                c = W.Circuit(n, [g], 1 if src == "param" else 0)
+                plan = dq.Plan(c, dtype, fusion=fusion, fold_init=False)
+                p = torch.tensor([0.3], dtype=torch.float64, device=dev) if src == "param" else None
+                ws = plan.workspace(1, False, 0, None, dev)
+                dq.apply_circuit(plan, st, p, None, from_zero=False, ws=ws)
+                torch.cuda.synchronize()
+                plan.profile_enable(True)
+                plan.profile_read(reset=True)
+                for _ in range(args.sweep_reps):
+                    dq.apply_circuit(plan, st, p, None, from_zero=False, ws=ws)
+                torch.cuda.synchronize()
+                pr = plan.profile_read(reset=True)
+                fam = "fwd_tile" if fusion else "gate"
+                v = pr[fam]
+                if not v["launches"]:
+                    continue
+                ms = v["ms"] / v["launches"]
+                gbs = (v["bytes"] / v["launches"] / 1e9) / (ms / 1e3)
+                row = {"dtype": dtype, "n": n, "op": op, "wires": list(wires),
+                       "phys_bits": [n - 1 - w for w in wires], "path": "tile" if fusion else "plain",
+                       "ms": ms, "GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
+                       "bytes": v["bytes"] / v["launches"]}
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+        del st
+        torch.cuda.empty_cache()
+    # a device-to-device copy of the same size, as the practical ceiling
+    n = args.sweep_qubits
+    a = torch.empty((1 << n,), dtype=torch.complex64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.sweep_reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.sweep_reps
+    print(json.dumps({"op": "device copy (torch)", "n": n, "ms": ms, "GBps": 2 * a.numel() * 8 / 1e9 / (ms / 1e3)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,9 +170,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg5", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
     ap.add_argument("--tile-bits", type=int, default=0)
+    ap.add_argument("--dense-fuse", type=int, default=0, choices=[0, 4, 5],
+                    help="forward sweep as fused dense k-qubit blocks on the matrix cores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-layers", type=int, default=2)
+    ap.add_argument("--sweeps", action="store_true", help="single-gate sweep bandwidth table instead of the step")
+    ap.add_argument("--sweep-qubits", type=int, default=30)
+    ap.add_argument("--sweep-reps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -114,11 +196,14 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.sweeps:
+        sweeps(args)
+        return
     cid = int(args.workload[3:])
     wl = W.config(cid)
     c = wl.circuit
     B = wl.batch
-    plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits)
+    plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits, dense_fuse=args.dense_fuse)
     obs = dq.Observable(c.n, wl.observables)
     params = torch.as_tensor(wl.params, dtype=torch.float64, device=dev)
     data = None if wl.data is None else torch.as_tensor(wl.data, dtype=torch.float64, device=dev)
@@ -167,13 +252,24 @@ def main():
                           "GBps": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["bytes"] and v["ms"] else None}
     dom = max((k for k in prof if prof[k]["launches"]), key=lambda k: prof[k]["ms"])
     d = prof[dom]
+    avg_s = d["ms"] / d["launches"] / 1e3
     bytes_per_launch = d["bytes"] / d["launches"]
-    achieved = (bytes_per_launch / 1e9) / (d["ms"] / d["launches"] / 1e3)
+    flops_per_launch = d["flops"] / d["launches"]
+    gbs = (bytes_per_launch / 1e9) / avg_s
+    tflops = (flops_per_launch / 1e12) / avg_s
     traffic = load_traffic(args.workload, dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": bytes_per_launch,
-                "avg_launch_ms": d["ms"] / d["launches"]}
+    hbm = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": bytes_per_launch,
+           "avg_launch_ms": avg_s * 1e3}
+    alu = {"bound": "alu", "kernel": dom, "achieved": tflops, "peak": ALU_PEAK_TFLOPS[wl.dtype], "unit": "TFLOP/s",
+           "frac": tflops / ALU_PEAK_TFLOPS[wl.dtype], "traffic": traffic,
+           "algorithmic_flops_per_launch": flops_per_launch, "avg_launch_ms": avg_s * 1e3}
+    # the register-tile passes trade HBM sweeps for arithmetic: report the
+    # resource the kernel is closer to saturating, the other one beside it
+    roofline, other_roof = (alu, hbm) if alu["frac"] > hbm["frac"] else (hbm, alu)
+    for k, v in prof.items():
+        if v["launches"] and v["flops"]:
+            kernels[k]["TFLOPs"] = (v["flops"] / 1e12) / (v["ms"] / 1e3)
 
     # sanity of the timed result (outside the timed region)
     Ev = float(E[0, 0].item())
@@ -234,11 +330,13 @@ def main():
                    "grad": "adjoint" if grad else "none", "observable_terms": len(wl.observables[0]),
                    "seed": wl.seed, "parallelism": "none (one GPU)"},
         "roofline": roofline,
+        "roofline_other": other_roof,
         "cpu_baseline": cpu,
         "plain_path": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "kernels": kernels,
-        "plan": {"fwd_tile_passes": st["fwd_tile_passes"], "adj_steps": st["adj_steps"],
+        "plan": {"fwd_tile_passes": st["fwd_tile_passes"], "fwd_dense_blocks": st["fwd_dense_blocks"],
+                 "adj_steps": st["adj_steps"],
                  "folded_gates": st["folded_gates"], "tile_bits": st["tile_bits"]},
         "checks": checks,
         "source_hash": kernel_source_hash(),

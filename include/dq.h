@@ -117,8 +117,9 @@ typedef struct {
                              4 for complex128); 1..6 (complex128: 1..5) */
     int32_t fold_init;    /* 1 (default): fold the leading one-qubit gates of every wire into
                              the initial product-state write when applying from |0..0> */
-    int32_t dense_fuse;   /* 0 (default): off; 4 or 5: fuse runs of gates that stay on <= k
-                             wires into one dense 2^k x 2^k block applied on the matrix cores */
+    int32_t dense_fuse;   /* 0 (default): register tiles; 4 or 5: the forward sweep groups gates
+                             into dense blocks on k wires (product of the gate matrices, formed
+                             on the device in double) applied on the matrix cores (MFMA) */
 } dq_options;
 
 typedef struct dq_plan_s *dq_plan;
@@ -213,15 +214,51 @@ enum {
     DQ_PROF_LAMBDA = 5,     /* adjoint seed lambda = sum w H psi */
     DQ_PROF_INIT = 6,       /* state initialisation / product-state write */
     DQ_PROF_OTHER = 7,      /* matrix preparation, final gradient reduction, copies */
-    DQ_PROF_KINDS = 8
+    DQ_PROF_DENSE = 8,      /* dense 4- or 5-qubit block on the matrix cores */
+    DQ_PROF_KINDS = 9
 };
 typedef struct {
     int64_t launches[DQ_PROF_KINDS];
     double ms[DQ_PROF_KINDS];
     double bytes[DQ_PROF_KINDS];
+    double flops[DQ_PROF_KINDS];   /* algorithmic real floating-point operations: per
+                                      amplitude, 14 for a dense 2x2 complex matrix, 6 for a
+                                      real, RX-form or diagonal one, 6 for a two-qubit
+                                      diagonal, 3 for a gradient term, 0 for permutations */
 } dq_profile;
 dq_status dq_profile_enable(dq_plan plan, int32_t on);
 dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset);
+
+/* Uneven batches (paper 4.3, batched processing), several circuits of
+ * different sizes at once.  A multi-plan binds nplans plans of one dtype and
+ * one observable handle per circuit.  Circuit c has one sample: its state is
+ * the 2^{n_c} amplitudes at packed offset state_off[c] of one state buffer,
+ * its parameters the nparams_c doubles at param_off[c] of one parameter
+ * buffer (dq_multi_layout fills both offset arrays; circuits are packed in
+ * order, each state 256-byte aligned).  Register-tile passes of equal depth
+ * of all circuits run as one kernel launch over every circuit's tiles, so a
+ * step needs as many tile launches as the deepest circuit has passes, not
+ * their sum; plans whose programs are not pure tile passes of the common
+ * tile shape run through the single-plan path inside the same calls.  All
+ * per-circuit offsets are fixed at creation, so the launch sequence can be
+ * captured in a HIP graph and replayed.  Data-encoded gates are not
+ * supported here (ndata must be 0). */
+typedef struct dq_multi_s *dq_multi;
+dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs, int32_t nplans);
+void dq_multi_destroy(dq_multi m);
+/* total packed state amplitudes / parameters / expectation outputs, and the
+ * per-circuit offsets (arrays of nplans, each nullable) */
+dq_status dq_multi_layout(dq_multi m, int64_t *state_amps, int64_t *param_count, int64_t *nout,
+                          int64_t *state_off, int64_t *param_off, int64_t *out_off);
+dq_status dq_multi_workspace_size(dq_multi m, size_t *bytes);
+/* every circuit from |0...0> (leading one-qubit gates folded) */
+dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *ws, size_t ws_bytes, void *stream);
+/* out[out_off[c] + o] = expectation of observable o of circuit c (float64, device) */
+dq_status dq_multi_expval(dq_multi m, const void *states, double *out, void *ws, size_t ws_bytes, void *stream);
+/* adjoint gradients of sum_c sum_o grad_out[out_off[c] + o] E_c,o; the states
+ * are consumed; grad_params packed like params */
+dq_status dq_multi_adjoint_grad(dq_multi m, void *states, const double *params, const double *grad_out,
+                                double *grad_params, void *ws, size_t ws_bytes, void *stream);
 
 /* Description of the last error on this thread ("" after success). */
 const char *dq_last_error(void);

@@ -9,8 +9,8 @@ the engine without a built library raises.
 """
 from ._lib import DqError, LIB_PATH, lib  # noqa: F401
 
-__all__ = ["DqError", "LIB_PATH", "lib", "Plan", "Observable", "state_init", "apply_circuit", "expval",
-           "adjoint_grad", "expectation", "ExpvalFunction"]
+__all__ = ["DqError", "LIB_PATH", "lib", "Plan", "Observable", "state_init", "apply_circuit", "expval", "autotune",
+           "adjoint_grad", "expectation", "ExpvalFunction", "Multi"]
 
 
 def __getattr__(name):

@@ -22,8 +22,10 @@ C64, C128 = 0, 1
 
 EXPORTS = ["dq_plan_create", "dq_plan_destroy", "dq_plan_get_stats", "dq_obs_create", "dq_obs_destroy",
            "dq_workspace_size", "dq_state_init", "dq_apply_circuit", "dq_expval", "dq_adjoint_grad",
-           "dq_last_error", "dq_version", "dq_profile_enable", "dq_profile_read"]
-PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other"]
+           "dq_last_error", "dq_version", "dq_profile_enable", "dq_profile_read",
+           "dq_multi_create", "dq_multi_destroy", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
+           "dq_multi_expval", "dq_multi_adjoint_grad"]
+PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other", "dense"]
 
 
 class DqGate(ctypes.Structure):
@@ -39,14 +41,14 @@ class DqOptions(ctypes.Structure):
     _fields_ = [("fusion", c_int32), ("tile_bits", c_int32), ("fold_init", c_int32), ("dense_fuse", c_int32)]
 
 
-class DqPlanStats(ctypes.Structure):
+class DqPlanStats(ctypes.Structure):  # noqa: E302
     _fields_ = [("nqubits", c_int32), ("dtype", c_int32), ("ngates", c_int64), ("fwd_steps", c_int64),
                 ("fwd_tile_passes", c_int64), ("fwd_dense_blocks", c_int64), ("adj_steps", c_int64),
                 ("folded_gates", c_int64), ("grad_gates", c_int64), ("tile_bits", c_int32)]
 
 
 class DqProfile(ctypes.Structure):
-    _fields_ = [("launches", c_int64 * 8), ("ms", c_double * 8), ("bytes", c_double * 8)]
+    _fields_ = [("launches", c_int64 * 9), ("ms", c_double * 9), ("bytes", c_double * 9), ("flops", c_double * 9)]
 
 
 class DqError(RuntimeError):
@@ -82,10 +84,21 @@ def lib():
                                       c_size_t, vp]
         L.dq_profile_enable.argtypes = [vp, c_int32]
         L.dq_profile_read.argtypes = [vp, POINTER(DqProfile), c_int32]
+        L.dq_multi_create.argtypes = [POINTER(vp), POINTER(vp), POINTER(vp), c_int32]
+        L.dq_multi_destroy.argtypes = [vp]
+        L.dq_multi_destroy.restype = None
+        i64p = POINTER(c_int64)
+        L.dq_multi_layout.argtypes = [vp, i64p, i64p, i64p, i64p, i64p, i64p]
+        L.dq_multi_workspace_size.argtypes = [vp, POINTER(c_size_t)]
+        L.dq_multi_apply.argtypes = [vp, vp, vp, vp, c_size_t, vp]
+        L.dq_multi_expval.argtypes = [vp, vp, vp, vp, c_size_t, vp]
+        L.dq_multi_adjoint_grad.argtypes = [vp, vp, vp, vp, vp, vp, c_size_t, vp]
         L.dq_last_error.restype = c_char_p
         L.dq_version.restype = c_int32
         for f in ("dq_plan_create", "dq_plan_get_stats", "dq_obs_create", "dq_workspace_size", "dq_state_init",
-                  "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read"):
+                  "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read",
+                  "dq_multi_create", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
+                  "dq_multi_expval", "dq_multi_adjoint_grad"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib

@@ -41,16 +41,31 @@ struct DSlot {
     int64_t off;               // complex offset inside one sample's matrix block
 };
 
+// A fused dense block: the product, in gate order, of nf one- and two-qubit
+// gates (factor table entries foff..foff+nf-1) that act inside the K block
+// bits bb[0..K-1] (bb[0] = most significant bit of the block index).
+struct DBlock {
+    int32_t k;
+    int32_t nf;
+    int32_t foff;
+    int32_t bb[5];
+    int64_t off;               // complex offset inside one sample's matrix block
+};
+
 // ---------------------------------------------------------------- tile passes
-// Tile-local bit q: 0..5 = lane bits (physical bits 0..5), 6..6+R-1 = register
-// bits (physical rbits[q-6]).
+// Tile-local bit q: 0..5 = lane bits, 6..6+R-1 = register bits.  Lane bits 0..2
+// are physical bits 0..2 in every pass (each group of 8 lanes reads 8
+// consecutive amplitudes); lane bits 3..5 are physical lbits[0..2] and
+// register bit q is physical rbits[q-6], chosen per pass.
 enum : int32_t {
     TK_1Q = 0,      // dense 2x2 on q0
     TK_1QDIAG = 1,  // diagonal 2x2 on q0 (entries m00, m11 of the slot)
     TK_CNOT = 2,    // control q0, target q1
     TK_CZ = 3,      // q0, q1
     TK_2QDIAG = 4,  // diagonal 4x4 on (q0 = msb, q1) (entries 0, 5, 10, 15 of the slot)
-    TK_SWAP = 5     // exchange q0 and q1
+    TK_SWAP = 5,    // exchange q0 and q1
+    TK_1QREAL = 6,  // real 2x2 on q0 (real parts of the slot)
+    TK_1QRX = 7     // [[c, i s], [i s, c]] on q0 (c = Re m00, s = Im m01)
 };
 
 struct TOp {
@@ -62,6 +77,20 @@ struct TOp {
 };
 
 enum : int32_t { MAX_TILE_R = 6, MAX_LSLOTS = 64 };
+
+// One circuit's tile pass inside a multi-circuit launch.  Offsets: st_off in
+// amplitudes from the packed state base; lam_off, mats_off, part_off in bytes
+// from the workspace base.  unit_begin: first work unit of this entry (units:
+// tiles in the forward, waves in the adjoint).
+struct MultiEntry {
+    int64_t st_off, lam_off, mats_off, part_off, unit_begin;
+    const TOp *ops;
+    const int32_t *lsg;
+    int32_t n, nops, nls, wps, ngrad;
+    int32_t rbits[MAX_TILE_R];
+    int32_t lbits[3];
+    int32_t tbits[MAX_TILE_R + 3];
+};
 
 // ---------------------------------------------------------------- observables
 // Terms grouped by X mask (physical bits).  With w = coef * i^{nY} (complex,
@@ -90,7 +119,9 @@ struct TileArgs {
     void *st;                  // state [B][2^n]
     void *lam;                 // adjoint state (adjoint passes only)
     int32_t n, R;
-    int32_t rbits[MAX_TILE_R];
+    int32_t rbits[MAX_TILE_R]; // physical bits of the register bits
+    int32_t lbits[3];          // physical bits of lane bits 3..5
+    int32_t tbits[MAX_TILE_R + 3];  // lbits and rbits together, ascending
     int64_t batch;
     const TOp *ops;
     int32_t nops, nlslots;
@@ -104,6 +135,10 @@ struct TileArgs {
 hipError_t launch_prepare(int dbl, const DGate *gates, const void *fixed, const DSlot *slots,
                           int32_t nslots, const double *params, int64_t pstride, const double *data,
                           int64_t dstride, void *mats, int64_t block, int64_t bm, hipStream_t s);
+hipError_t launch_prepare_blocks(int dbl, const DGate *gates, const void *fixed, const DBlock *blocks,
+                                 int32_t nblocks, const int32_t *factors, const double *params, int64_t pstride,
+                                 const double *data, int64_t dstride, void *mats, int64_t block, int64_t bm,
+                                 hipStream_t s);
 hipError_t launch_init_zero(int dbl, void *st, int32_t n, int64_t batch, hipStream_t s);
 hipError_t launch_init_copy(int dbl, void *st, const void *init, int32_t n, int64_t batch, hipStream_t s);
 hipError_t launch_init_product(int dbl, void *st, int32_t n, int64_t batch, const void *mats,
@@ -115,10 +150,19 @@ hipError_t launch_cnot(int dbl, void *st, int32_t n, int64_t batch, int32_t cbit
 hipError_t launch_cz(int dbl, void *st, int32_t n, int64_t batch, int32_t abit, int32_t bbit, hipStream_t s);
 hipError_t launch_gatek(int dbl, void *st, int32_t n, int64_t batch, int32_t k, const int32_t *bits,
                         const void *mats, int64_t mstride, int64_t off, hipStream_t s);
+// dense 2^k x 2^k block (k = 4, 5) on the matrix cores; needs n >= k + 5
+// (complex64) or n >= k + 4 (complex128)
+hipError_t launch_dense(int dbl, void *st, int32_t n, int64_t batch, int32_t k, const int32_t *bits, const void *mats,
+                        int64_t mstride, int64_t off, hipStream_t s);
 hipError_t launch_tile_fwd(int dbl, const TileArgs &a, hipStream_t s);
 hipError_t launch_tile_adj(int dbl, const TileArgs &a, hipStream_t s);
 // resident single-wave workgroups of the adjoint tile kernel on the current device
 int tile_adj_capacity(int dbl, int R);
+// multi-circuit tile passes: entries describe one depth of every circuit
+hipError_t launch_tile_fwd_multi(int dbl, int R, void *st, const void *ws, const MultiEntry *ents, int32_t nent,
+                                 int64_t units, hipStream_t s);
+hipError_t launch_tile_adj_multi(int dbl, int R, void *st, void *ws, const MultiEntry *ents, int32_t nent,
+                                 int64_t units, int32_t max_nls, hipStream_t s);
 hipError_t launch_grad_gate(int dbl, const void *psi, const void *lam, int32_t n, int64_t batch, int32_t gen,
                             int32_t bit0, int32_t bit1, double *partial, int32_t wps, int32_t ngrad,
                             int32_t gslot, hipStream_t s);

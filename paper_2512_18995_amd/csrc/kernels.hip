@@ -37,12 +37,42 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 #define DQ_SF(N, ...) static_for<0, (N)>([&](auto ic_) { constexpr int i = decltype(ic_)::value; __VA_ARGS__; })
+// The same, with a scheduling barrier after every 8 elements: loops that
+// issue cross-lane shuffles would otherwise hoist all of them and hold every
+// result in registers at once.
+#define DQ_SF8(N, ...)                                                       \
+    static_for<0, (N)>([&](auto ic_) {                                      \
+        constexpr int i = decltype(ic_)::value;                             \
+        __VA_ARGS__;                                                        \
+        if constexpr ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);      \
+    })
 
 // Read-only tables (op lists, gate matrices) are read through the constant
 // address space so that wave-uniform reads become scalar loads.
 template <typename T> using cptr = __attribute__((address_space(4))) const T *;
 template <typename T> __device__ __forceinline__ cptr<T> to_const(const T *p) { return (cptr<T>)(uintptr_t)p; }
 template <typename V> __device__ __forceinline__ V ldc(cptr<V> p, int k) { return V{p[k].x, p[k].y}; }
+// MultiEntry read field by field from the constant address space (scalar loads)
+__device__ __forceinline__ MultiEntry ld_entry(cptr<MultiEntry> ents, int e) {
+    MultiEntry E;
+    E.st_off = ents[e].st_off;
+    E.lam_off = ents[e].lam_off;
+    E.mats_off = ents[e].mats_off;
+    E.part_off = ents[e].part_off;
+    E.unit_begin = ents[e].unit_begin;
+    E.ops = ents[e].ops;
+    E.lsg = ents[e].lsg;
+    E.n = ents[e].n;
+    E.nops = ents[e].nops;
+    E.nls = ents[e].nls;
+    E.wps = ents[e].wps;
+    E.ngrad = ents[e].ngrad;
+    for (int k = 0; k < MAX_TILE_R; ++k) E.rbits[k] = ents[e].rbits[k];
+    for (int k = 0; k < 3; ++k) E.lbits[k] = ents[e].lbits[k];
+    for (int k = 0; k < MAX_TILE_R + 3; ++k) E.tbits[k] = ents[e].tbits[k];
+    return E;
+}
+
 __device__ __forceinline__ TOp ld_op(cptr<TOp> ops, int k) {
     const cptr<int32_t> w = (cptr<int32_t>)(ops + k);
     TOp o;
@@ -64,12 +94,15 @@ template <typename T> using cx = cpx<T>;
 using C64 = cpx<float>;
 using C128 = cpx<double>;
 
+__device__ __forceinline__ float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
     return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 // a * b + c
 template <typename V> __device__ __forceinline__ V cmac(V a, V b, V c) {
-    return V{fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
+    return V{fm(a.x, b.x, fm(-a.y, b.y, c.x)), fm(a.x, b.y, fm(a.y, b.x, c.y))};
 }
 template <typename V> __device__ __forceinline__ V cneg(V a) { return V{-a.x, -a.y}; }
 // component-wise select (a struct-valued ?: becomes a pointer select plus a
@@ -171,6 +204,64 @@ __global__ void k_prepare(const DGate *gates, const double2 *fixed, const DSlot 
             if (sl.dagger) e.y = -e.y;
             out[r * dim + c] = cx<T>{(T)e.x, (T)e.y};
         }
+}
+
+// One dense block per workgroup, one column per thread: the column starts
+// as a unit vector and every factor gate is applied to it as to a K-qubit
+// state (double precision), then the column is rounded once into the block.
+template <typename T>
+__global__ void k_prepare_block(const DGate *gates, const double2 *fixed, const DBlock *blocks, const int32_t *factors,
+                                const double *params, int64_t pstride, const double *data, int64_t dstride,
+                                cx<T> *mats, int64_t block) {
+    const DBlock bl = blocks[blockIdx.x];
+    const int64_t b = blockIdx.y;
+    const int D = 1 << bl.k, c = threadIdx.x;
+    if (c >= D) return;
+    double2 col[32];
+    for (int r = 0; r < D; ++r) col[r] = double2{r == c ? 1.0 : 0.0, 0.0};
+    double2 F[16];
+    for (int f = 0; f < bl.nf; ++f) {
+        const DGate g = gates[factors[bl.foff + f]];
+        double v = 1.0;
+        if (g.src == SRC_PARAM) v = params[b * pstride + g.idx];
+        else if (g.src == SRC_DATA) v = data[b * dstride + g.idx];
+        gate_matrix(g, g.scale * v, fixed, F);
+        // block index bit of each gate bit: bb[t] sits at bit (k-1-t) of the block index
+        int pos[2] = {0, 0};
+        for (int q = 0; q < g.nq; ++q)
+            for (int t = 0; t < bl.k; ++t)
+                if (bl.bb[t] == g.bits[q]) pos[q] = bl.k - 1 - t;
+        if (g.nq == 1) {
+            const int m = 1 << pos[0];
+            for (int r = 0; r < D; ++r) {
+                if (r & m) continue;
+                const double2 a0 = col[r], a1 = col[r | m];
+                col[r] = double2{F[0].x * a0.x - F[0].y * a0.y + F[1].x * a1.x - F[1].y * a1.y,
+                                 F[0].x * a0.y + F[0].y * a0.x + F[1].x * a1.y + F[1].y * a1.x};
+                col[r | m] = double2{F[2].x * a0.x - F[2].y * a0.y + F[3].x * a1.x - F[3].y * a1.y,
+                                     F[2].x * a0.y + F[2].y * a0.x + F[3].x * a1.y + F[3].y * a1.x};
+            }
+        } else {
+            const int m0 = 1 << pos[0], m1 = 1 << pos[1];   // gate bits[0] is the MSB of F's index
+            for (int r = 0; r < D; ++r) {
+                if (r & (m0 | m1)) continue;
+                const int idx[4] = {r, r | m1, r | m0, r | m0 | m1};
+                double2 a[4], o[4];
+                for (int q = 0; q < 4; ++q) a[q] = col[idx[q]];
+                for (int x = 0; x < 4; ++x) {
+                    double re = 0, im = 0;
+                    for (int q = 0; q < 4; ++q) {
+                        re += F[x * 4 + q].x * a[q].x - F[x * 4 + q].y * a[q].y;
+                        im += F[x * 4 + q].x * a[q].y + F[x * 4 + q].y * a[q].x;
+                    }
+                    o[x] = double2{re, im};
+                }
+                for (int q = 0; q < 4; ++q) col[idx[q]] = o[q];
+            }
+        }
+    }
+    cx<T> *out = mats + b * block + bl.off;
+    for (int r = 0; r < D; ++r) out[r * D + c] = cx<T>{(T)col[r].x, (T)col[r].y};
 }
 
 // ============================================================ init
@@ -323,7 +414,9 @@ __global__ __launch_bounds__(256) void k_gatek(cx<T> *st, int n, int64_t total, 
 // Tile-local index u = (register index i) << 6 | lane.  Bit q of u: lane bit
 // for q < 6, register bit q-6 otherwise.
 __device__ __forceinline__ bool tbit(int i, int lane, int q) {
-    return ((((unsigned)i << 6) | (unsigned)lane) >> q) & 1u;
+    // the lane half does not depend on i (hoisted out of the register loop);
+    // the register half is wave-uniform (scalar ALU)
+    return q < 6 ? ((lane >> q) & 1) : ((i >> (q - 6)) & 1);
 }
 
 template <int K> struct Pair {   // the i-th index pair (i0, i1) differing in register bit K
@@ -331,49 +424,93 @@ template <int K> struct Pair {   // the i-th index pair (i0, i1) differing in re
     static constexpr int hi(int i) { return lo(i) | (1 << K); }
 };
 
-template <typename V, int NR, int K>
-__device__ __forceinline__ void reg_1q(V (&v)[NR], V m00, V m01, V m10, V m11) {
+// Every op below updates NS state arrays of NR register amplitudes (NS = 1
+// in the forward sweep, 2 = (psi, lambda) in the adjoint sweep), so that one
+// dispatch serves both states and their arithmetic interleaves.
+#define DQ_NS(...) static_for<0, NS>([&](auto sc_) { constexpr int s_ = decltype(sc_)::value; __VA_ARGS__; })
+
+template <typename V, int NS, int NR, int K>
+__device__ __forceinline__ void reg_1q(V (&v)[NS][NR], V m00, V m01, V m10, V m11) {
     DQ_SF(NR / 2, {
         constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
-        const V a0 = v[i0], a1 = v[i1];
-        v[i0] = cmac(m00, a0, cmul(m01, a1));
-        v[i1] = cmac(m10, a0, cmul(m11, a1));
+        DQ_NS({
+            const V a0 = v[s_][i0], a1 = v[s_][i1];
+            v[s_][i0] = cmac(m00, a0, cmul(m01, a1));
+            v[s_][i1] = cmac(m10, a0, cmul(m11, a1));
+        });
     });
 }
 
-template <typename V, int NR, int K>
-__device__ __forceinline__ void reg_cnot(V (&v)[NR], int cq, int lane) {
+// real 2x2 (RY and products of RY, H, X, Z): 8 FMA per pair instead of 16
+template <typename V, int NS, int NR, int K, typename T>
+__device__ __forceinline__ void reg_1q_real(V (&v)[NS][NR], T m00, T m01, T m10, T m11) {
+    DQ_SF(NR / 2, {
+        constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
+        DQ_NS({
+            const V a0 = v[s_][i0], a1 = v[s_][i1];
+            v[s_][i0] = V{fm(m00, a0.x, m01 * a1.x), fm(m00, a0.y, m01 * a1.y)};
+            v[s_][i1] = V{fm(m10, a0.x, m11 * a1.x), fm(m10, a0.y, m11 * a1.y)};
+        });
+    });
+}
+
+// [[c, i s], [i s, c]] (RX and its dagger): 8 FMA per pair
+template <typename V, int NS, int NR, int K, typename T>
+__device__ __forceinline__ void reg_1q_rx(V (&v)[NS][NR], T c, T s) {
+    DQ_SF(NR / 2, {
+        constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
+        DQ_NS({
+            const V a0 = v[s_][i0], a1 = v[s_][i1];
+            v[s_][i0] = V{fm(c, a0.x, -s * a1.y), fm(c, a0.y, s * a1.x)};
+            v[s_][i1] = V{fm(c, a1.x, -s * a0.y), fm(c, a1.y, s * a0.x)};
+        });
+    });
+}
+
+template <typename V, int NS, int NR, int K>
+__device__ __forceinline__ void reg_1q_diag(V (&v)[NS][NR], V d0, V d1) {
+    DQ_SF(NR, { DQ_NS({ v[s_][i] = cmul(((i >> K) & 1) ? d1 : d0, v[s_][i]); }); });
+}
+
+template <typename V, int NS, int NR, int K>
+__device__ __forceinline__ void reg_cnot(V (&v)[NS][NR], int cq, int lane) {
     DQ_SF(NR / 2, {
         constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
         const bool c = tbit(i0, lane, cq);
-        const V a0 = v[i0], a1 = v[i1];
-        v[i0] = csel(c, a1, a0);
-        v[i1] = csel(c, a0, a1);
+        DQ_NS({
+            const V a0 = v[s_][i0], a1 = v[s_][i1];
+            v[s_][i0] = csel(c, a1, a0);
+            v[s_][i1] = csel(c, a0, a1);
+        });
     });
 }
 
 // swap of two register bits K1 < K2
-template <typename V, int NR, int K1, int K2>
-__device__ __forceinline__ void reg_swap(V (&v)[NR]) {
+template <typename V, int NS, int NR, int K1, int K2>
+__device__ __forceinline__ void reg_swap(V (&v)[NS][NR]) {
     DQ_SF(NR, {
         if constexpr (((i >> K1) & 1) && !((i >> K2) & 1)) {
             constexpr int j = i ^ (1 << K1) ^ (1 << K2);
-            const V t = v[i];
-            v[i] = v[j];
-            v[j] = t;
+            DQ_NS({
+                const V t = v[s_][i];
+                v[s_][i] = v[s_][j];
+                v[s_][j] = t;
+            });
         }
     });
 }
 
 // swap of lane bit l with register bit K
-template <typename V, int NR, int K>
-__device__ __forceinline__ void lane_reg_swap(V (&v)[NR], int l, int lane) {
+template <typename V, int NS, int NR, int K>
+__device__ __forceinline__ void lane_reg_swap(V (&v)[NS][NR], int l, int lane) {
     const bool hl = (lane >> l) & 1;
-    DQ_SF(NR / 2, {
+    DQ_SF8(NR / 2, {
         constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
-        const V o0 = shfl_xor_c(v[i1], 1 << l), o1 = shfl_xor_c(v[i0], 1 << l);
-        v[i0] = csel(hl, o0, v[i0]);
-        v[i1] = csel(hl, v[i1], o1);
+        DQ_NS({
+            const V o0 = shfl_xor_c(v[s_][i1], 1 << l), o1 = shfl_xor_c(v[s_][i0], 1 << l);
+            v[s_][i0] = csel(hl, o0, v[s_][i0]);
+            v[s_][i1] = csel(hl, v[s_][i1], o1);
+        });
     });
 }
 
@@ -399,20 +536,20 @@ __device__ __forceinline__ T reg_xy_sum(const V (&v)[NR], const V (&l)[NR], bool
     default: break;                                                           \
     }
 
-template <typename V, int NR, int K1>
-__device__ __forceinline__ void reg_swap_k2(V (&v)[NR], int k2) {
+template <typename V, int NS, int NR, int K1>
+__device__ __forceinline__ void reg_swap_k2(V (&v)[NS][NR], int k2) {
     switch (k2) {
-    case 1: if constexpr (NR > 2 && K1 < 1) reg_swap<V, NR, K1, 1>(v); break;
-    case 2: if constexpr (NR > 4 && K1 < 2) reg_swap<V, NR, K1, 2>(v); break;
-    case 3: if constexpr (NR > 8 && K1 < 3) reg_swap<V, NR, K1, 3>(v); break;
-    case 4: if constexpr (NR > 16 && K1 < 4) reg_swap<V, NR, K1, 4>(v); break;
-    case 5: if constexpr (NR > 32 && K1 < 5) reg_swap<V, NR, K1, 5>(v); break;
+    case 1: if constexpr (NR > 2 && K1 < 1) reg_swap<V, NS, NR, K1, 1>(v); break;
+    case 2: if constexpr (NR > 4 && K1 < 2) reg_swap<V, NS, NR, K1, 2>(v); break;
+    case 3: if constexpr (NR > 8 && K1 < 3) reg_swap<V, NS, NR, K1, 3>(v); break;
+    case 4: if constexpr (NR > 16 && K1 < 4) reg_swap<V, NS, NR, K1, 4>(v); break;
+    case 5: if constexpr (NR > 32 && K1 < 5) reg_swap<V, NS, NR, K1, 5>(v); break;
     default: break;
     }
 }
 
-template <typename T, int NR>
-__device__ __forceinline__ void apply_op(cx<T> (&v)[NR], const TOp &op, cptr<cx<T>> m, int lane) {
+template <typename T, int NS, int NR>
+__device__ __forceinline__ void apply_op(cx<T> (&v)[NS][NR], const TOp &op, cptr<cx<T>> m, int lane) {
     using V = cx<T>;
     switch (op.kind) {
     case TK_1Q: {
@@ -420,37 +557,79 @@ __device__ __forceinline__ void apply_op(cx<T> (&v)[NR], const TOp &op, cptr<cx<
         if (op.q0 < 6) {
             const bool hi = (lane >> op.q0) & 1;
             const V cs = csel(hi, m11, m00), co = csel(hi, m10, m01);
-            DQ_SF(NR, { v[i] = cmac(cs, v[i], cmul(co, shfl_xor_c(v[i], 1 << op.q0))); });
+            DQ_SF8(NR, { DQ_NS({ v[s_][i] = cmac(cs, v[s_][i], cmul(co, shfl_xor_c(v[s_][i], 1 << op.q0))); }); });
         } else {
-            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q<V, NR, K_>(v, m00, m01, m10, m11)));
+            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q<V, NS, NR, K_>(v, m00, m01, m10, m11)));
+        }
+        break;
+    }
+    case TK_1QREAL: {
+        const T m00 = m[op.slot].x, m01 = m[op.slot + 1].x, m10 = m[op.slot + 2].x, m11 = m[op.slot + 3].x;
+        if (op.q0 < 6) {
+            const bool hi = (lane >> op.q0) & 1;
+            const T cs = hi ? m11 : m00, co = hi ? m10 : m01;
+            DQ_SF8(NR, {
+                DQ_NS({
+                    const V o = shfl_xor_c(v[s_][i], 1 << op.q0);
+                    v[s_][i] = V{fm(cs, v[s_][i].x, co * o.x), fm(cs, v[s_][i].y, co * o.y)};
+                });
+            });
+        } else {
+            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q_real<V, NS, NR, K_, T>(v, m00, m01, m10, m11)));
+        }
+        break;
+    }
+    case TK_1QRX: {
+        const T c = m[op.slot].x, sn = m[op.slot + 1].y;   // m01 = i s
+        if (op.q0 < 6) {
+            DQ_SF8(NR, {
+                DQ_NS({
+                    const V o = shfl_xor_c(v[s_][i], 1 << op.q0);
+                    v[s_][i] = V{fm(c, v[s_][i].x, -sn * o.y), fm(c, v[s_][i].y, sn * o.x)};
+                });
+            });
+        } else {
+            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q_rx<V, NS, NR, K_, T>(v, c, sn)));
         }
         break;
     }
     case TK_1QDIAG: {
         const V d0 = ldc(m, op.slot), d1 = ldc(m, op.slot + 3);
-        DQ_SF(NR, { v[i] = cmul(csel(tbit(i, lane, op.q0), d1, d0), v[i]); });
+        if (op.q0 < 6) {
+            const V d = csel(((lane >> op.q0) & 1) != 0, d1, d0);   // one factor per lane
+            DQ_SF(NR, { DQ_NS({ v[s_][i] = cmul(d, v[s_][i]); }); });
+        } else {
+            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q_diag<V, NS, NR, K_>(v, d0, d1)));
+        }
         break;
     }
     case TK_CNOT: {
         if (op.q1 < 6) {
-            DQ_SF(NR, {
-                const V o = shfl_xor_c(v[i], 1 << op.q1);
-                v[i] = csel(tbit(i, lane, op.q0), o, v[i]);
+            DQ_SF8(NR, {
+                const bool c = tbit(i, lane, op.q0);
+                DQ_NS({
+                    const V o = shfl_xor_c(v[s_][i], 1 << op.q1);
+                    v[s_][i] = csel(c, o, v[s_][i]);
+                });
             });
         } else {
-            DQ_REG_DISPATCH(op.q1 - 6, NR, (reg_cnot<V, NR, K_>(v, op.q0, lane)));
+            DQ_REG_DISPATCH(op.q1 - 6, NR, (reg_cnot<V, NS, NR, K_>(v, op.q0, lane)));
         }
         break;
     }
     case TK_CZ: {
-        DQ_SF(NR, { v[i] = csel(tbit(i, lane, op.q0) && tbit(i, lane, op.q1), cneg(v[i]), v[i]); });
+        DQ_SF(NR, {
+            const bool c = tbit(i, lane, op.q0) && tbit(i, lane, op.q1);
+            DQ_NS({ v[s_][i] = csel(c, cneg(v[s_][i]), v[s_][i]); });
+        });
         break;
     }
     case TK_2QDIAG: {
         const V d0 = ldc(m, op.slot), d1 = ldc(m, op.slot + 5), d2 = ldc(m, op.slot + 10), d3 = ldc(m, op.slot + 15);
         DQ_SF(NR, {
             const bool a = tbit(i, lane, op.q0), b = tbit(i, lane, op.q1);
-            v[i] = cmul(csel(a, csel(b, d3, d2), csel(b, d1, d0)), v[i]);
+            const V d = csel(a, csel(b, d3, d2), csel(b, d1, d0));
+            DQ_NS({ v[s_][i] = cmul(d, v[s_][i]); });
         });
         break;
     }
@@ -459,14 +638,16 @@ __device__ __forceinline__ void apply_op(cx<T> (&v)[NR], const TOp &op, cptr<cx<
         if (b < 6) {
             const int mask = (1 << a) | (1 << b);
             const bool differ = ((lane >> a) ^ (lane >> b)) & 1;
-            DQ_SF(NR, {
-                const V o = shfl_xor_c(v[i], mask);
-                v[i] = csel(differ, o, v[i]);
+            DQ_SF8(NR, {
+                DQ_NS({
+                    const V o = shfl_xor_c(v[s_][i], mask);
+                    v[s_][i] = csel(differ, o, v[s_][i]);
+                });
             });
         } else if (a < 6) {
-            DQ_REG_DISPATCH(b - 6, NR, (lane_reg_swap<V, NR, K_>(v, a, lane)));
+            DQ_REG_DISPATCH(b - 6, NR, (lane_reg_swap<V, NS, NR, K_>(v, a, lane)));
         } else {
-            DQ_REG_DISPATCH(a - 6, NR, (reg_swap_k2<V, NR, K_>(v, b - 6)));
+            DQ_REG_DISPATCH(a - 6, NR, (reg_swap_k2<V, NS, NR, K_>(v, b - 6)));
         }
         break;
     }
@@ -502,7 +683,7 @@ __device__ __forceinline__ T gen_local(const cx<T> (&v)[NR], const cx<T> (&l)[NR
     case GEN_Y: {
         const bool isY = op.gen == GEN_Y;
         if (op.q0 < 6) {
-            DQ_SF(NR, {
+            DQ_SF8(NR, {
                 V o = shfl_xor_c(v[i], 1 << op.q0);
                 if (isY) o = csel(((lane >> op.q0) & 1) != 0, V{-o.y, o.x}, V{o.y, -o.x});
                 s += l[i].x * o.y - l[i].y * o.x;
@@ -517,12 +698,24 @@ __device__ __forceinline__ T gen_local(const cx<T> (&v)[NR], const cx<T> (&l)[NR
     return s;
 }
 
+// first amplitude of tile t: the tile index fills every physical bit that is
+// not a tile bit (bits 0..2 and the 3 + R chosen bits are zero)
 template <int R>
-__device__ __forceinline__ int64_t tile_base(int64_t t, const int32_t *rb) {
-    int64_t base = t << 6;
+__device__ __forceinline__ int64_t tile_base(int64_t t, const int32_t *tb) {
+    int64_t base = t << 3;
 #pragma unroll
-    for (int k = 0; k < R; ++k) base = insert_zero(base, rb[k]);
+    for (int k = 0; k < R + 3; ++k) base = insert_zero(base, tb[k]);
     return base;
+}
+
+// this lane's offset inside a tile: lane bits 0..2 -> physical 0..2,
+// lane bits 3..5 -> lbits[0..2]
+__device__ __forceinline__ int64_t lane_off(int lane, const int32_t *lb) {
+    int64_t o = lane & 7;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if ((lane >> (3 + k)) & 1) o += int64_t(1) << lb[k];
+    return o;
 }
 
 template <int R>
@@ -534,67 +727,289 @@ __device__ __forceinline__ int64_t reg_off(int i, const int32_t *rb) {
     return o;
 }
 
+// occupancy target (waves per SIMD) of the register tiles: two for the
+// largest tiles, more for small ones
+template <typename T, int R> constexpr int tile_waves() { return (1 << R) * sizeof(T) >= 256 ? 1 : ((1 << R) * sizeof(T) >= 128 ? 2 : 3); }
+// the adjoint holds two states per lane: two waves per SIMD up to 16
+// complex64 (8 complex128) amplitudes per state
+template <typename T, int R> constexpr int adj_waves() { return (1 << R) * sizeof(T) >= 128 ? 1 : ((1 << R) * sizeof(T) >= 64 ? 2 : 4); }
+
+// One forward tile: load 2^R amplitudes per lane, run the op list, store.
 template <typename T, int R>
-__global__ __launch_bounds__(64) void k_tile_fwd(TileArgs a) {
+__device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, const int32_t *rbits, cptr<TOp> ops,
+                                         int nops, cptr<cx<T>> m, int lane) {
     using V = cx<T>;
     constexpr int NR = 1 << R;
-    const int lane = threadIdx.x;
-    const int tshift = a.n - 6 - R;
-    const int64_t total = a.batch << tshift;
-    const int64_t tmask = (int64_t(1) << tshift) - 1;
-    const cptr<TOp> ops = to_const(a.ops);
-    V v[NR];
-    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        const int64_t b = tile >> tshift;
-        V *tp = (V *)a.st + (b << a.n) + tile_base<R>(tile & tmask, a.rbits);   // wave-uniform
-        const cptr<V> m = to_const((const V *)a.mats + b * a.mstride);
-        DQ_SF(NR, { v[i] = (tp + reg_off<R>(i, a.rbits))[lane]; });
-        for (int k = 0; k < a.nops; ++k) {
-            const TOp op = ld_op(ops, k);
-            apply_op<T, NR>(v, op, m, lane);
+    V v[1][NR];
+    {
+        V *tp = st + base;
+        DQ_SF(NR, { v[0][i] = (tp + reg_off<R>(i, rbits))[lo]; });
+    }
+    for (int k = 0; k < nops; ++k) {
+        const TOp op = ld_op(ops, k);
+        apply_op<T, 1, NR>(v, op, m, lane);
+    }
+    // recompute the addresses for the stores rather than keeping the loads'
+    // 2^R per-lane pointers alive across the op loop
+    asm volatile("" : "+s"(base));
+    {
+        V *tp = st + base;
+        DQ_SF(NR, { (tp + reg_off<R>(i, rbits))[lo] = v[0][i]; });
+    }
+}
+
+// One adjoint work unit: tiles t = w, w + wps, ... of one sample; per-lane
+// float64 accumulators in LDS, reduced over the wave into partial[lslot].
+template <typename T, int R>
+__device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, int n, const int32_t *rbits,
+                                         const int32_t *lbits, const int32_t *tbits, cptr<TOp> ops, int nops, int nls,
+                                         cptr<cx<T>> m, int64_t w, int64_t wps, double *partial_row,
+                                         const int32_t *lslot_gslot, double *acc, int lane) {
+    using V = cx<T>;
+    constexpr int NR = 1 << R;
+    const int64_t tps = int64_t(1) << (n - 6 - R);
+    for (int s = 0; s < nls; ++s) acc[s * 64 + lane] = 0.0;
+    const int64_t lo = lane_off(lane, lbits);
+    V v[2][NR];   // [0] = psi, [1] = lambda
+    for (int64_t t = w; t < tps; t += wps) {
+        int64_t base = sbase + tile_base<R>(t, tbits);   // wave-uniform
+        {
+            V *pp = st + base;
+            V *qp = lam + base;
+            DQ_SF(NR, {
+                v[0][i] = (pp + reg_off<R>(i, rbits))[lo];
+                v[1][i] = (qp + reg_off<R>(i, rbits))[lo];
+            });
         }
-        DQ_SF(NR, { (tp + reg_off<R>(i, a.rbits))[lane] = v[i]; });
+        for (int k = 0; k < nops; ++k) {
+            const TOp op = ld_op(ops, k);
+            if (op.lslot >= 0) acc[op.lslot * 64 + lane] += (double)gen_local<T, NR>(v[0], v[1], op, lane);
+            apply_op<T, 2, NR>(v, op, m, lane);
+        }
+        asm volatile("" : "+s"(base));
+        {
+            V *pp = st + base;
+            V *qp = lam + base;
+            DQ_SF(NR, {
+                (pp + reg_off<R>(i, rbits))[lo] = v[0][i];
+                (qp + reg_off<R>(i, rbits))[lo] = v[1][i];
+            });
+        }
+    }
+    for (int s = 0; s < nls; ++s) {
+        double x = acc[s * 64 + lane];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) partial_row[lslot_gslot[s]] = x;
     }
 }
 
 template <typename T, int R>
-__global__ __launch_bounds__(64) void k_tile_adj(TileArgs a) {
+__global__ __launch_bounds__(64, (tile_waves<T, R>())) void k_tile_fwd(TileArgs a) {
     using V = cx<T>;
-    constexpr int NR = 1 << R;
-    extern __shared__ double acc[];   // [nlslots][64], one entry per lane
     const int lane = threadIdx.x;
-    const int64_t b = blockIdx.y;
-    const int w = blockIdx.x;
     const int tshift = a.n - 6 - R;
-    const int64_t tps = int64_t(1) << tshift;
-    const cptr<TOp> ops = to_const(a.ops);
-    const cptr<V> m = to_const((const V *)a.mats + b * a.mstride);
-    for (int s = 0; s < a.nlslots; ++s) acc[s * 64 + lane] = 0.0;
-    V v[NR], l[NR];
-    for (int64_t t = w; t < tps; t += a.wps) {
-        const int64_t base = (b << a.n) + tile_base<R>(t, a.rbits);   // wave-uniform
-        V *pp = (V *)a.st + base;
-        V *qp = (V *)a.lam + base;
-        DQ_SF(NR, {
-            v[i] = (pp + reg_off<R>(i, a.rbits))[lane];
-            l[i] = (qp + reg_off<R>(i, a.rbits))[lane];
-        });
-        for (int k = 0; k < a.nops; ++k) {
-            const TOp op = ld_op(ops, k);
-            if (op.lslot >= 0) acc[op.lslot * 64 + lane] += (double)gen_local<T, NR>(v, l, op, lane);
-            apply_op<T, NR>(v, op, m, lane);
-            apply_op<T, NR>(l, op, m, lane);
-        }
-        DQ_SF(NR, {
-            (pp + reg_off<R>(i, a.rbits))[lane] = v[i];
-            (qp + reg_off<R>(i, a.rbits))[lane] = l[i];
-        });
+    const int64_t total = a.batch << tshift;
+    const int64_t tmask = (int64_t(1) << tshift) - 1;
+    const int64_t lo = lane_off(lane, a.lbits);
+    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int64_t b = tile >> tshift;
+        const int64_t base = (b << a.n) + tile_base<R>(tile & tmask, a.tbits);   // wave-uniform
+        fwd_tile<T, R>((V *)a.st, base, lo, a.rbits, to_const(a.ops), a.nops,
+                       to_const((const V *)a.mats + b * a.mstride), lane);
     }
-    for (int s = 0; s < a.nlslots; ++s) {
-        double x = acc[s * 64 + lane];
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj(TileArgs a) {
+    using V = cx<T>;
+    extern __shared__ double acc[];   // [nlslots][64], one entry per lane
+    const int64_t b = blockIdx.y;
+    adj_unit<T, R>((V *)a.st, (V *)a.lam, b << a.n, a.n, a.rbits, a.lbits, a.tbits, to_const(a.ops), a.nops,
+                   a.nlslots, to_const((const V *)a.mats + b * a.mstride), blockIdx.x, a.wps,
+                   a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, threadIdx.x);
+}
+
+// ---------------------------------------------------------------- uneven batches
+// One launch runs the tile pass of the same depth for every circuit of a
+// multi-plan: work unit u belongs to the entry e with unit_begin[e] <= u <
+// unit_begin[e + 1]; pointers are base + per-entry offsets.
+__device__ __forceinline__ int find_entry(cptr<MultiEntry> ents, int nent, int64_t u) {
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {                       // last entry with unit_begin <= u
+        const int mid = (lo + hi + 1) >> 1;
+        if (ents[mid].unit_begin <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(64, (tile_waves<T, R>())) void k_tile_fwd_multi(cx<T> *st, const char *ws,
+                                                                             const MultiEntry *ents_, int nent,
+                                                                             int64_t units) {
+    using V = cx<T>;
+    const cptr<MultiEntry> ents = to_const(ents_);
+    const int lane = threadIdx.x;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int e = find_entry(ents, nent, u);
+        const MultiEntry E = ld_entry(ents, e);
+        const int64_t base = E.st_off + tile_base<R>(u - E.unit_begin, E.tbits);
+        fwd_tile<T, R>(st, base, lane_off(lane, E.lbits), E.rbits, to_const(E.ops), E.nops,
+                       to_const((const V *)(ws + E.mats_off)), lane);
+    }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj_multi(cx<T> *st, char *ws,
+                                                                            const MultiEntry *ents_, int nent) {
+    using V = cx<T>;
+    extern __shared__ double acc[];
+    const cptr<MultiEntry> ents = to_const(ents_);
+    const int64_t u = blockIdx.x;
+    const int e = find_entry(ents, nent, u);
+    const MultiEntry E = ld_entry(ents, e);
+    const int64_t w = u - E.unit_begin;
+    adj_unit<T, R>(st, (V *)(ws + E.lam_off), E.st_off, E.n, E.rbits, E.lbits, E.tbits, to_const(E.ops), E.nops,
+                   E.nls, to_const((const V *)(ws + E.mats_off)), w, E.wps,
+                   (double *)(ws + E.part_off) + w * (int64_t)E.ngrad, E.lsg, acc, threadIdx.x);
+}
+
+// ============================================================ matrix-core dense blocks
+// y = U x for a dense 2^K x 2^K complex U on K target bits (K = 4, 5), as the
+// real product [[Re U, -Im U], [Im U, Re U]] (2D x 2D, D = 2^K) times
+// [Re x; Im x] (2D x columns).  Columns are the 2^(n-K) index values of the
+// other bits; a wave owns 32 consecutive columns (complex64) or 16 (complex128),
+// so with no target bit among the lowest 5 (4) physical bits each row is one
+// contiguous run.  complex64: v_mfma_f32_32x32x2_f32, lane l supplies
+// B[k = l/32][n = l%32] and A[m = l%32][k = l/32], and receives
+// D[8 (v/4) + 4 (l/32) + v%4][l%32] in accumulator v.  complex128:
+// v_mfma_f64_16x16x4_f64, B[k = l/16][n = l%16], A[m = l%16][k = l/16],
+// D[l/16 + 4 v][l%16] (lane layout checked on the device).
+struct DenseBits {
+    int32_t bits[5];     // physical bits, bits[0] = MSB of U's index
+    int32_t sorted[5];   // ascending
+};
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__device__ __forceinline__ int64_t dense_row_off(int r, const DenseBits &db) {
+    int64_t o = 0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        if (lane == 0) a.partial[(b * a.wps + w) * (int64_t)a.ngrad + a.lslot_gslot[s]] = x;
+    for (int t = 0; t < K; ++t)
+        if ((r >> (K - 1 - t)) & 1) o += int64_t(1) << db.bits[t];
+    return o;
+}
+
+// entry (m, c) of the real 2D x 2D form of U (row-major complex, dimension D)
+template <int D, typename T>
+__device__ __forceinline__ T real_form(cptr<cx<T>> U, int m, int c) {
+    const int mr = m & (D - 1), cr = c & (D - 1);
+    const bool im_row = m >= D, im_col = c >= D;
+    const T re = U[mr * D + cr].x, im = U[mr * D + cr].y;
+    return im_row ? (im_col ? re : im) : (im_col ? -im : re);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_f32(C64 *st, int n, int64_t groups, DenseBits db, const C64 *mats,
+                                                   int64_t mstride, int64_t off) {
+    constexpr int D = 1 << K, MB = 2 * D / 32, KK = D, XR = D / 2;
+    const int lane = threadIdx.x & 63, kq = lane >> 5, nn = lane & 31;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = (gridDim.x * (int64_t)blockDim.x) >> 6;
+    const int gshift = n - K - 5;
+    float A[MB][KK];
+    int64_t cur = -1;
+    for (int64_t g = wave; g < groups; g += nwaves) {
+        const int64_t b = g >> gshift;
+        if (b != cur) {
+            const cptr<C64> U = to_const(mats + b * mstride + off);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) A[mb][kk] = real_form<D, float>(U, 32 * mb + nn, 2 * kk + kq);
+            cur = b;
+        }
+        int64_t col = ((g & ((int64_t(1) << gshift) - 1)) << 5) | nn;
+#pragma unroll
+        for (int t = 0; t < K; ++t) col = insert_zero(col, db.sorted[t]);
+        C64 *p = st + (b << n) + col;
+        C64 x[XR];
+#pragma unroll
+        for (int k2 = 0; k2 < XR; ++k2) x[k2] = p[dense_row_off<K>(2 * k2 + kq, db)];
+        f32x16 acc[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x16{};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const float bv = kk < XR ? x[kk].x : x[kk - XR].y;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[mb][kk], bv, acc[mb], 0, 0, 0);
+        }
+        if constexpr (MB == 2) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = 8 * (v >> 2) + 4 * kq + (v & 3);
+                p[dense_row_off<K>(r, db)] = C64{acc[0][v], acc[1][v]};
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int r = 8 * (v >> 2) + 4 * kq + (v & 3);   // rows < 16: real parts; row + 16: imaginary
+                p[dense_row_off<K>(r, db)] = C64{acc[0][v], acc[0][v + 8]};
+            }
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_f64(C128 *st, int n, int64_t groups, DenseBits db, const C128 *mats,
+                                                   int64_t mstride, int64_t off) {
+    constexpr int D = 1 << K, MB = 2 * D / 16, KK = 2 * D / 4, XR = D / 4;
+    const int lane = threadIdx.x & 63, kq = lane >> 4, nn = lane & 15;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = (gridDim.x * (int64_t)blockDim.x) >> 6;
+    const int gshift = n - K - 4;
+    double A[MB][KK];
+    int64_t cur = -1;
+    for (int64_t g = wave; g < groups; g += nwaves) {
+        const int64_t b = g >> gshift;
+        if (b != cur) {
+            const cptr<C128> U = to_const(mats + b * mstride + off);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) A[mb][kk] = real_form<D, double>(U, 16 * mb + nn, 4 * kk + kq);
+            cur = b;
+        }
+        int64_t col = ((g & ((int64_t(1) << gshift) - 1)) << 4) | nn;
+#pragma unroll
+        for (int t = 0; t < K; ++t) col = insert_zero(col, db.sorted[t]);
+        C128 *p = st + (b << n) + col;
+        C128 x[XR];     // rows r = 4 k2 + kq
+#pragma unroll
+        for (int k2 = 0; k2 < XR; ++k2) x[k2] = p[dense_row_off<K>(4 * k2 + kq, db)];
+        f64x4 acc[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = f64x4{};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            // B[k][n] = X[4 kk + k][n]: real rows 0..D-1, imaginary rows D..2D-1
+            const double bv = kk < XR ? x[kk].x : x[kk - XR].y;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[mb][kk], bv, acc[mb], 0, 0, 0);
+        }
+        // block mb covers rows 16 mb .. 16 mb + 15; real parts in the first MB/2 blocks;
+        // accumulator v of lane l holds row 16 mb + l/16 + 4 v, column l % 16
+#pragma unroll
+        for (int mb = 0; mb < MB / 2; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * mb + kq + 4 * v;
+                p[dense_row_off<K>(r, db)] = C128{acc[mb][v], acc[mb + MB / 2][v]};
+            }
     }
 }
 
@@ -659,7 +1074,58 @@ __global__ void k_grad_final(const double *partial, int64_t batch, int wps, int 
     out[i] = sum;
 }
 
-constexpr int EXP_TM = 16;
+constexpr int EXP_TM = 32;
+
+// Partial sums S_t = sum_j (-1)^{|j & z_t|} conj(psi_{j^x}) psi_j over this
+// block's share of the amplitudes, for up to EXP_TM terms of one X-mask
+// group.  DIAG (x = 0): the product is |psi_j|^2, real.
+template <typename T, bool DIAG>
+__device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t x, cptr<DTerm> terms, int c0,
+                                             int nt, double *row, int eb, double (*red)[2 * EXP_TM]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t z[EXP_TM];
+    double ar[EXP_TM], ai[EXP_TM];
+#pragma unroll
+    for (int t = 0; t < EXP_TM; ++t) {
+        z[t] = t < nt ? terms[c0 + t].zmask : 0;
+        ar[t] = 0.0;
+        ai[t] = 0.0;
+    }
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)eb * blockDim.x) {
+        const cx<T> a = p[j];
+        double pr, pi = 0.0;
+        if (DIAG) {
+            pr = (double)(a.x * a.x + a.y * a.y);
+        } else {
+            const cx<T> o = p[j ^ (int64_t)x];
+            pr = (double)(o.x * a.x + o.y * a.y);
+            pi = (double)(o.x * a.y - o.y * a.x);
+        }
+#pragma unroll
+        for (int t = 0; t < EXP_TM; ++t) {
+            if (t < nt) {
+                const bool neg = __popcll((uint64_t)j & z[t]) & 1;
+                ar[t] += neg ? -pr : pr;
+                if (!DIAG) ai[t] += neg ? -pi : pi;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < EXP_TM; ++t) {
+        if (t < nt) {
+            const double xr = wave_sum(ar[t]), xi = DIAG ? 0.0 : wave_sum(ai[t]);
+            if (lane == 0) {
+                red[wv][2 * t] = xr;
+                red[wv][2 * t + 1] = xi;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nt)
+        row[c0 * 2 + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    __syncthreads();
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_expval_part(const cx<T> *st, int n, const DGroup *groups, int ngroups,
@@ -668,48 +1134,16 @@ __global__ __launch_bounds__(256) void k_expval_part(const cx<T> *st, int n, con
     const int64_t b = blockIdx.y;
     const int64_t N = int64_t(1) << n;
     const cx<T> *p = st + b * N;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const cptr<DGroup> gp = to_const(groups);
+    const cptr<DTerm> tp = to_const(terms);
+    double *row = partial + (b * eb + blockIdx.x) * (int64_t)nterms * 2;   // this block's [nterms][2]
     for (int g = 0; g < ngroups; ++g) {
-        const DGroup G = groups[g];
-        for (int c0 = G.t0; c0 < G.t1; c0 += EXP_TM) {
-            const int nt = (G.t1 - c0) < EXP_TM ? (G.t1 - c0) : EXP_TM;
-            uint64_t z[EXP_TM];
-            double ar[EXP_TM], ai[EXP_TM];
-#pragma unroll
-            for (int t = 0; t < EXP_TM; ++t) {
-                z[t] = t < nt ? terms[c0 + t].zmask : 0;
-                ar[t] = 0.0;
-                ai[t] = 0.0;
-            }
-            for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
-                 j += (int64_t)eb * blockDim.x) {
-                const cx<T> a = p[j], o = p[j ^ (int64_t)G.xmask];
-                const double pr = (double)(o.x * a.x + o.y * a.y), pi = (double)(o.x * a.y - o.y * a.x);
-#pragma unroll
-                for (int t = 0; t < EXP_TM; ++t) {
-                    if (t < nt) {
-                        const bool neg = __popcll((uint64_t)j & z[t]) & 1;
-                        ar[t] += neg ? -pr : pr;
-                        ai[t] += neg ? -pi : pi;
-                    }
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < EXP_TM; ++t) {
-                if (t < nt) {
-                    const double xr = wave_sum(ar[t]), xi = wave_sum(ai[t]);
-                    if (lane == 0) {
-                        red[wv][2 * t] = xr;
-                        red[wv][2 * t + 1] = xi;
-                    }
-                }
-            }
-            __syncthreads();
-            if (threadIdx.x < 2 * nt) {
-                const double s = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
-                partial[((b * eb + blockIdx.x) * (int64_t)nterms + c0) * 2 + threadIdx.x] = s;
-            }
-            __syncthreads();
+        const uint64_t x = gp[g].xmask;
+        const int t0 = gp[g].t0, t1 = gp[g].t1;
+        for (int c0 = t0; c0 < t1; c0 += EXP_TM) {
+            const int nt = (t1 - c0) < EXP_TM ? (t1 - c0) : EXP_TM;
+            if (x == 0) expval_chunk<T, true>(p, N, x, tp, c0, nt, row, eb, red);
+            else expval_chunk<T, false>(p, N, x, tp, c0, nt, row, eb, red);
         }
     }
 }
@@ -735,32 +1169,36 @@ __global__ void k_expval_final(const double *partial, int64_t batch, int eb, con
 }
 
 // lambda_j = sum_k gout[b, obs_k] * coef_k i^{nY_k} (-1)^{|(j^x_k) & z_k|} psi_{j ^ x_k}
+// (for the X-free group the terms collapse into one factor d(j) psi_j)
 template <typename T>
 __global__ __launch_bounds__(256) void k_lambda(const cx<T> *psi, cx<T> *lam, int n, int64_t total, const DGroup *groups,
                                                 int ngroups, const DTerm *terms, const double *gout, int nobs) {
     const int64_t mask = (int64_t(1) << n) - 1;
+    const cptr<DGroup> gp = to_const(groups);
+    const cptr<DTerm> tp = to_const(terms);
+    const cptr<double> go = to_const(gout);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = i >> n, j = i & mask;
         const cx<T> *p = psi + (b << n);
         double ar = 0.0, ai = 0.0;
         for (int g = 0; g < ngroups; ++g) {
-            const DGroup G = groups[g];
-            const int64_t jx = j ^ (int64_t)G.xmask;
+            const uint64_t x = gp[g].xmask;
+            const int t0 = gp[g].t0, t1 = gp[g].t1;
+            const int64_t jx = j ^ (int64_t)x;
+            // d = sum_t w_t (-1)^{|jx & z_t|}, w_t = gout[b, obs_t] * coef_t i^{nY_t}
+            double dr = 0.0, di = 0.0;
+            for (int t = t0; t < t1; ++t) {
+                const double w = go[b * nobs + tp[t].obs];
+                const double wr = w * tp[t].wr, wi = w * tp[t].wi;
+                const bool neg = __popcll((uint64_t)jx & tp[t].zmask) & 1;
+                dr += neg ? -wr : wr;
+                di += neg ? -wi : wi;
+            }
             const cx<T> o = p[jx];
             const double ox = (double)o.x, oy = (double)o.y;
-            for (int t = G.t0; t < G.t1; ++t) {
-                const DTerm tm = terms[t];
-                const double go = gout[b * nobs + tm.obs];
-                const double cr = go * tm.wr, ci = go * tm.wi;
-                double tr = cr * ox - ci * oy, ti = cr * oy + ci * ox;
-                if (__popcll((uint64_t)jx & tm.zmask) & 1) {
-                    tr = -tr;
-                    ti = -ti;
-                }
-                ar += tr;
-                ai += ti;
-            }
+            ar += dr * ox - di * oy;
+            ai += dr * oy + di * ox;
         }
         lam[i] = cx<T>{(T)ar, (T)ai};
     }
@@ -781,6 +1219,20 @@ hipError_t launch_prepare(int dbl, const DGate *gates, const void *fixed, const 
                            params, pstride, data, dstride, (C128 *)mats, block);
     else
         hipLaunchKernelGGL(k_prepare<float>, grid, dim3(64), 0, s, gates, (const double2 *)fixed, slots, nslots,
+                           params, pstride, data, dstride, (C64 *)mats, block);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_prepare_blocks(int dbl, const DGate *gates, const void *fixed, const DBlock *blocks, int32_t nblocks,
+                                 const int32_t *factors, const double *params, int64_t pstride, const double *data,
+                                 int64_t dstride, void *mats, int64_t block, int64_t bm, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    dim3 grid((unsigned)nblocks, (unsigned)bm);
+    if (dbl)
+        hipLaunchKernelGGL(k_prepare_block<double>, grid, dim3(32), 0, s, gates, (const double2 *)fixed, blocks, factors,
+                           params, pstride, data, dstride, (C128 *)mats, block);
+    else
+        hipLaunchKernelGGL(k_prepare_block<float>, grid, dim3(32), 0, s, gates, (const double2 *)fixed, blocks, factors,
                            params, pstride, data, dstride, (C64 *)mats, block);
     DQ_LAUNCH_RET;
 }
@@ -907,6 +1359,27 @@ static int resident_waves(K kernel, size_t lds, int key) {
     return c;
 }
 
+hipError_t launch_dense(int dbl, void *st, int32_t n, int64_t batch, int32_t k, const int32_t *bits, const void *mats,
+                        int64_t mstride, int64_t off, hipStream_t s) {
+    DenseBits db;
+    for (int t = 0; t < 5; ++t) db.bits[t] = db.sorted[t] = t < k ? bits[t] : 0;
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b)
+            if (db.sorted[b] < db.sorted[a]) { int t = db.sorted[a]; db.sorted[a] = db.sorted[b]; db.sorted[b] = t; }
+    const int colbits = dbl ? 4 : 5;
+    if (k < 4 || k > 5 || n < k + colbits) return hipErrorInvalidValue;
+    const int64_t groups = batch << (n - k - colbits);
+    const unsigned grid = grid_for(groups * 64, 256, 4096);
+    if (dbl) {
+        if (k == 4) hipLaunchKernelGGL(k_dense_f64<4>, dim3(grid), dim3(256), 0, s, (C128 *)st, n, groups, db, (const C128 *)mats, mstride, off);
+        else hipLaunchKernelGGL(k_dense_f64<5>, dim3(grid), dim3(256), 0, s, (C128 *)st, n, groups, db, (const C128 *)mats, mstride, off);
+    } else {
+        if (k == 4) hipLaunchKernelGGL(k_dense_f32<4>, dim3(grid), dim3(256), 0, s, (C64 *)st, n, groups, db, (const C64 *)mats, mstride, off);
+        else hipLaunchKernelGGL(k_dense_f32<5>, dim3(grid), dim3(256), 0, s, (C64 *)st, n, groups, db, (const C64 *)mats, mstride, off);
+    }
+    DQ_LAUNCH_RET;
+}
+
 static unsigned tile_grid(int64_t tiles, int resident) {
     // one resident wave per slot; each wave walks a strided subset of the tiles
     const int64_t cap = resident > 0 ? resident : 4096;
@@ -989,6 +1462,56 @@ hipError_t launch_tile_adj(int dbl, const TileArgs &a, hipStream_t s) {
         tile_adj_t<float>(a, s);
     }
     DQ_LAUNCH_RET;
+}
+
+template <typename T>
+static hipError_t fwd_multi_t(int R, void *st, const void *ws, const MultiEntry *e, int32_t n, int64_t units,
+                              hipStream_t s) {
+    const unsigned g = (unsigned)(units < 16384 ? units : 16384);
+    switch (R) {
+    case 3: hipLaunchKernelGGL((k_tile_fwd_multi<T, 3>), dim3(g), dim3(64), 0, s, (cx<T> *)st, (const char *)ws, e, n, units); break;
+    case 4: hipLaunchKernelGGL((k_tile_fwd_multi<T, 4>), dim3(g), dim3(64), 0, s, (cx<T> *)st, (const char *)ws, e, n, units); break;
+    case 5:
+        if constexpr (sizeof(T) == 4) {
+            hipLaunchKernelGGL((k_tile_fwd_multi<T, 5>), dim3(g), dim3(64), 0, s, (cx<T> *)st, (const char *)ws, e, n, units);
+            break;
+        }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_fwd_multi(int dbl, int R, void *st, const void *ws, const MultiEntry *ents, int32_t nent,
+                                 int64_t units, hipStream_t s) {
+    if (units <= 0) return hipSuccess;
+    return dbl ? fwd_multi_t<double>(R, st, ws, ents, nent, units, s) : fwd_multi_t<float>(R, st, ws, ents, nent, units, s);
+}
+
+template <typename T>
+static hipError_t adj_multi_t(int R, void *st, void *ws, const MultiEntry *e, int32_t n, int64_t units, size_t lds,
+                              hipStream_t s) {
+    const unsigned g = (unsigned)units;
+    switch (R) {
+    case 3: hipLaunchKernelGGL((k_tile_adj_multi<T, 3>), dim3(g), dim3(64), lds, s, (cx<T> *)st, (char *)ws, e, n); break;
+    case 4:
+        if constexpr (sizeof(T) == 4) {
+            hipLaunchKernelGGL((k_tile_adj_multi<T, 4>), dim3(g), dim3(64), lds, s, (cx<T> *)st, (char *)ws, e, n);
+            break;
+        }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_adj_multi(int dbl, int R, void *st, void *ws, const MultiEntry *ents, int32_t nent,
+                                 int64_t units, int32_t max_nls, hipStream_t s) {
+    if (units <= 0) return hipSuccess;
+    if (max_nls > MAX_LSLOTS || units > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * 64 * (max_nls > 0 ? max_nls : 1);
+    return dbl ? adj_multi_t<double>(R, st, ws, ents, nent, units, lds, s)
+               : adj_multi_t<float>(R, st, ws, ents, nent, units, lds, s);
 }
 
 hipError_t launch_grad_gate(int dbl, const void *psi, const void *lam, int32_t n, int64_t batch, int32_t gen,

@@ -66,7 +66,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct dq_plan_s;
 namespace {
 hipEvent_t prof_event(dq_plan_s &p);
-void prof_push(dq_plan_s &p, int kind, int nl, hipEvent_t a, hipEvent_t b, double bytes);
+void prof_push(dq_plan_s &p, int kind, int nl, hipEvent_t a, hipEvent_t b, double bytes, double flops);
 bool prof_on(const dq_plan_s &p);
 
 // Brackets one or more launches with a pair of events when profiling is on.
@@ -76,6 +76,7 @@ struct ProfScope {
     double bytes;
     hipStream_t s;
     hipEvent_t a = nullptr;
+    double flops = 0;
     ProfScope(dq_plan_s &pl, int k, int nlaunch, double b, hipStream_t st) : p(pl), kind(k), nl(nlaunch), bytes(b), s(st) {
         if (prof_on(p)) {
             a = prof_event(p);
@@ -86,31 +87,35 @@ struct ProfScope {
         if (a) {
             hipEvent_t b = prof_event(p);
             (void)hipEventRecord(b, s);
-            prof_push(p, kind, nl, a, b, bytes);
+            prof_push(p, kind, nl, a, b, bytes, flops);
             a = nullptr;
         }
     }
 };
 
 // ================================================================ plan
-enum StepKind { ST_TILE = 0, ST_G1, ST_CNOT, ST_CZ, ST_GK, ST_GRAD };
+enum StepKind { ST_TILE = 0, ST_G1, ST_CNOT, ST_CZ, ST_GK, ST_GRAD, ST_DENSE };
 
 struct Step {
     int kind = 0;
     int R = 0;
     int32_t rbits[MAX_TILE_R] = {0};
+    int32_t lbits[3] = {0};
+    int32_t tbits[MAX_TILE_R + 3] = {0};
     int64_t op0 = 0, nops = 0;      // into plan.ops
     int64_t ls0 = 0, nls = 0;       // into plan.lsg
     int k = 0;
     int32_t bits[5] = {0};          // per-gate: physical bits, bits[0] = matrix MSB / control
     int64_t slot = 0;
     int gen = 0, gslot = -1;
+    double flops_per_amp = 0;       // algorithmic flops per amplitude of one state
 };
 
 struct Program {
     std::vector<Step> steps;
     int64_t slot_lo = 0, slot_hi = 0;  // slot index range used (for prepare)
-    int64_t tile_passes = 0;
+    int64_t blk_lo = 0, blk_hi = 0;    // fused dense block range used
+    int64_t tile_passes = 0, dense_steps = 0;
 };
 
 struct DevData {
@@ -118,6 +123,8 @@ struct DevData {
     DGate *gates = nullptr;
     double2 *fixed = nullptr;
     DSlot *slots = nullptr;
+    DBlock *blocks = nullptr;
+    int32_t *factors = nullptr;
     TOp *ops = nullptr;
     int32_t *lsg = nullptr;
     int64_t *fold = nullptr;
@@ -136,6 +143,8 @@ struct dq_plan_s {
     std::vector<DGate> gates;
     std::vector<double2> fixed;
     std::vector<DSlot> slots;
+    std::vector<DBlock> blocks;         // fused dense blocks (dense_fuse)
+    std::vector<int32_t> factors;       // their factor gate lists
     int64_t block = 0;                  // complex elements per sample's matrix block
     std::vector<TOp> ops;
     std::vector<int32_t> lsg;
@@ -158,7 +167,7 @@ struct dq_plan_s {
         int kind;
         int nl;
         hipEvent_t a, b;
-        double bytes;
+        double bytes, flops;
     };
     std::vector<PRec> precs;
     dq_profile acc{};
@@ -185,8 +194,8 @@ hipEvent_t prof_event(dq_plan_s &p) {
     p.evused++;
     return e;
 }
-void prof_push(dq_plan_s &p, int kind, int nl, hipEvent_t a, hipEvent_t b, double bytes) {
-    if (a && b) p.precs.push_back({kind, nl, a, b, bytes});
+void prof_push(dq_plan_s &p, int kind, int nl, hipEvent_t a, hipEvent_t b, double bytes, double flops) {
+    if (a && b) p.precs.push_back({kind, nl, a, b, bytes, flops});
 }
 double state_bytes(const dq_plan_s &p, int64_t batch) { return (double)batch * std::ldexp(1.0, p.n) * (p.dbl ? 16 : 8); }
 
@@ -219,14 +228,15 @@ struct Planner {
         const DGate &G = p.gates[g];
         if (G.op == OP_UNITARY && G.nq != 1) return false;
         int hi = 0;
-        for (int i = 0; i < G.nq; ++i) hi += G.bits[i] >= 6;
-        return hi <= R;
+        for (int i = 0; i < G.nq; ++i) hi += G.bits[i] >= 3;
+        return hi <= R + 3;
     }
     bool diff(int g) const { return adjoint && p.gates[g].src != SRC_NONE && is_rotation(p.gates[g].op); }
 
     // Greedy in-order selection of the gates one tile pass can execute when
-    // the register bits are S (grown up to R bits while scanning).  Returns
-    // the executed gate positions (indices into `rem`).
+    // the free tile bits are S (grown up to R + 3 bits while scanning; bits
+    // 0..2 are in every tile).  Returns the executed gate positions (indices
+    // into `rem`).
     std::vector<int> select(const std::vector<int> &rem, uint64_t &S, int seed) const {
         uint64_t blocked = 0;
         std::vector<int> out;
@@ -236,8 +246,8 @@ struct Planner {
             int q[5], nq;
             gbits(rem[seed], q, nq);
             for (int i = 0; i < nq; ++i)
-                if (q[i] >= 6) S |= 1ull << q[i];
-            if (popc(S) > R) return out;
+                if (q[i] >= 3) S |= 1ull << q[i];
+            if (popc(S) > R + 3) return out;
         }
         for (size_t r = 0; r < rem.size(); ++r) {
             const int g = rem[r];
@@ -246,9 +256,9 @@ struct Planner {
             uint64_t Q = 0, need = 0;
             for (int i = 0; i < nq; ++i) {
                 Q |= 1ull << q[i];
-                if (q[i] >= 6) need |= 1ull << q[i];
+                if (q[i] >= 3) need |= 1ull << q[i];
             }
-            if ((Q & blocked) || !tile_ok(g) || (diff(g) && lslots >= 32) || popc(S | need) > R) {
+            if ((Q & blocked) || !tile_ok(g) || (diff(g) && lslots >= 32) || popc(S | need) > R + 3) {
                 blocked |= Q;
                 continue;
             }
@@ -277,15 +287,103 @@ struct Planner {
             s.kind = ST_CNOT;
         } else if (G.op == OP_CZ) {
             s.kind = ST_CZ;
+        } else if (G.op == OP_UNITARY && G.nq >= 4 && p.opt.fusion && p.n >= G.nq + (p.dbl ? 4 : 5)) {
+            s.kind = ST_DENSE;           // matrix cores
+            s.slot = p.slots[add_slot(p, 1 << G.nq, {g}, adjoint ? 1 : 0)].off;
+            ++prog.dense_steps;
         } else {
             s.kind = G.nq == 1 ? ST_G1 : ST_GK;
             s.slot = p.slots[add_slot(p, 1 << G.nq, {g}, adjoint ? 1 : 0)].off;
         }
+        s.flops_per_amp = G.op == OP_CNOT || G.op == OP_CZ || G.op == OP_SWAP ? 0.0 : (G.nq == 1 ? 14.0 : 8.0 * (1 << G.nq) - 2.0);
         prog.steps.push_back(s);
     }
 
     std::vector<int> gslot_of;   // gate -> gradient slot
     int grad_slot(int g) const { return gslot_of[g]; }
+
+    // Greedy in-order selection for a fused dense block on at most K bits.
+    std::vector<int> select_dense(const std::vector<int> &rem, uint64_t &W, int seed, int K) const {
+        uint64_t blocked = 0;
+        std::vector<int> out;
+        auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
+        auto ok = [&](const DGate &G) { return G.nq <= 2; };
+        if (seed >= 0) {
+            const DGate &G = p.gates[rem[seed]];
+            for (int i = 0; i < G.nq; ++i) W |= 1ull << G.bits[i];
+            if (popc(W) > K) return out;
+        }
+        for (size_t r = 0; r < rem.size(); ++r) {
+            const DGate &G = p.gates[rem[r]];
+            uint64_t Q = 0;
+            for (int i = 0; i < G.nq; ++i) Q |= 1ull << G.bits[i];
+            if ((Q & blocked) || !ok(G) || popc(W | Q) > K) {
+                blocked |= Q;
+                continue;
+            }
+            W |= Q;
+            out.push_back((int)r);
+        }
+        return out;
+    }
+
+    // Forward plan of fused K-qubit dense blocks applied on the matrix cores.
+    void plan_dense(Program &prog, std::vector<int> order, int K) {
+        prog.slot_lo = (int64_t)p.slots.size();
+        prog.blk_lo = (int64_t)p.blocks.size();
+        std::vector<int> rem = order;
+        while (!rem.empty()) {
+            const int g0 = rem[0];
+            uint64_t bestW = 0;
+            std::vector<int> best;
+            if (p.gates[g0].nq <= 2) {
+                int tried = 0;
+                for (size_t r = 0; r < rem.size() && tried < 48; ++r) {
+                    if (p.gates[rem[r]].nq > 2) continue;
+                    ++tried;
+                    uint64_t W = 0;
+                    std::vector<int> sel = select_dense(rem, W, (int)r, K);
+                    if (sel.size() > best.size()) {
+                        best = sel;
+                        bestW = W;
+                    }
+                }
+            }
+            if (best.empty()) {
+                emit_pergate(prog, g0);
+                rem.erase(rem.begin());
+                continue;
+            }
+            for (int b = 0; b < p.n && __builtin_popcountll(bestW) < K; ++b) bestW |= 1ull << b;
+            DBlock bl{};
+            bl.k = K;
+            bl.nf = (int32_t)best.size();
+            bl.foff = (int32_t)p.factors.size();
+            int t = 0;
+            for (int b = p.n - 1; b >= 0; --b)            // most significant block bit first
+                if (bestW >> b & 1) bl.bb[t++] = b;
+            for (int r : best) p.factors.push_back(rem[r]);
+            bl.off = p.block;
+            p.block += (int64_t)(1 << K) * (1 << K);
+            p.blocks.push_back(bl);
+            Step st;
+            st.kind = ST_DENSE;
+            st.k = K;
+            for (int i = 0; i < K; ++i) st.bits[i] = bl.bb[i];
+            st.slot = bl.off;
+            st.flops_per_amp = 8.0 * (1 << K) - 2.0;
+            prog.steps.push_back(st);
+            ++prog.dense_steps;
+            std::vector<char> done(rem.size(), 0);
+            for (int r : best) done[r] = 1;
+            std::vector<int> nrem;
+            for (size_t r = 0; r < rem.size(); ++r)
+                if (!done[r]) nrem.push_back(rem[r]);
+            rem.swap(nrem);
+        }
+        prog.slot_hi = (int64_t)p.slots.size();
+        prog.blk_hi = (int64_t)p.blocks.size();
+    }
 
     void plan(Program &prog, std::vector<int> order, bool fuse_1q) {
         prog.slot_lo = (int64_t)p.slots.size();
@@ -310,7 +408,7 @@ struct Planner {
             for (size_t r = 0; r < rem.size() && tried < 48; ++r) {
                 const DGate &G = p.gates[rem[r]];
                 bool hi = false;
-                for (int i = 0; i < G.nq; ++i) hi |= G.bits[i] >= 6;
+                for (int i = 0; i < G.nq; ++i) hi |= G.bits[i] >= 3;
                 if (!hi || !tile_ok(rem[r])) continue;
                 ++tried;
                 uint64_t S = 0;
@@ -325,20 +423,44 @@ struct Planner {
                 rem.erase(rem.begin());
                 continue;
             }
-            // pad the register set to exactly R bits
-            for (int b = 6; b < p.n && __builtin_popcountll(bestS) < R; ++b) bestS |= 1ull << b;
+            // pad the free set to exactly R + 3 bits
+            for (int b = 3; b < p.n && __builtin_popcountll(bestS) < R + 3; ++b) bestS |= 1ull << b;
+            // lane bits 3..5: the three free bits that see the fewest
+            // data-moving ops (those need cross-lane shuffles); the rest are
+            // register bits
+            int moves[64] = {0};
+            for (int r : best) {
+                const DGate &G = p.gates[rem[r]];
+                const bool diag = is_diag1(G.op) || G.op == OP_CZ || G.op == OP_CP || G.op == OP_RZZ;
+                if (diag) continue;
+                if (G.op == OP_CNOT) moves[G.bits[1]] += 1;
+                else
+                    for (int i = 0; i < G.nq; ++i) moves[G.bits[i]] += 1;
+            }
+            std::vector<int> freeb;
+            for (int b = 3; b < p.n; ++b)
+                if (bestS >> b & 1) freeb.push_back(b);
+            std::stable_sort(freeb.begin(), freeb.end(), [&](int x, int y) { return moves[x] < moves[y]; });
             Step st;
             st.kind = ST_TILE;
             st.R = R;
-            int nr = 0, local[64];
+            int local[64];
             for (int b = 0; b < 64; ++b) local[b] = -1;
-            for (int b = 0; b < 6; ++b) local[b] = b;
-            for (int b = 6; b < p.n; ++b)
-                if (bestS >> b & 1) {
-                    st.rbits[nr] = b;
-                    local[b] = 6 + nr;
-                    ++nr;
-                }
+            for (int b = 0; b < 3; ++b) local[b] = b;
+            std::vector<int> lanes(freeb.begin(), freeb.begin() + 3), regs(freeb.begin() + 3, freeb.end());
+            std::sort(lanes.begin(), lanes.end());
+            std::sort(regs.begin(), regs.end());
+            for (int k = 0; k < 3; ++k) {
+                st.lbits[k] = lanes[k];
+                local[lanes[k]] = 3 + k;
+            }
+            for (int k = 0; k < R; ++k) {
+                st.rbits[k] = regs[k];
+                local[regs[k]] = 6 + k;
+            }
+            std::vector<int> all(freeb);
+            std::sort(all.begin(), all.end());
+            for (int k = 0; k < R + 3; ++k) st.tbits[k] = all[k];
             st.op0 = (int64_t)p.ops.size();
             st.ls0 = (int64_t)p.lsg.size();
             std::vector<int> last_op(64, -1);     // per physical bit: index (in p.ops) of the last op touching it
@@ -386,7 +508,35 @@ struct Planner {
                 p.ops.push_back(op);
                 op_slot.push_back(slot_idx);
             }
+            // cheapest kernel form of each one-qubit slot: diagonal (RZ, Z),
+            // real (RY, H, X, Z and their products), RX form, or dense
+            for (int64_t k = st.op0; k < (int64_t)p.ops.size(); ++k) {
+                TOp &o = p.ops[k];
+                if (o.kind != TK_1Q && o.kind != TK_1QDIAG) continue;
+                const DSlot &sl = p.slots[op_slot[k - st.op0]];
+                bool diag = true, real = true;
+                for (int f = 0; f < sl.nf; ++f) {
+                    const int op = p.gates[sl.f[f]].op;
+                    diag = diag && is_diag1(op);
+                    real = real && (op == OP_RY || op == OP_H || op == OP_X || op == OP_Z);
+                }
+                if (diag) o.kind = TK_1QDIAG;
+                else if (real) o.kind = TK_1QREAL;
+                else if (sl.nf == 1 && p.gates[sl.f[0]].op == OP_RX) o.kind = TK_1QRX;
+                else o.kind = TK_1Q;
+            }
             st.nops = (int64_t)p.ops.size() - st.op0;
+            for (int64_t k = st.op0; k < (int64_t)p.ops.size(); ++k) {
+                const TOp &o = p.ops[k];
+                double f = 0;
+                switch (o.kind) {
+                case TK_1Q: f = 14; break;
+                case TK_1QREAL: case TK_1QRX: case TK_1QDIAG: case TK_2QDIAG: f = 6; break;
+                default: f = 0; break;
+                }
+                st.flops_per_amp += f;
+                if (o.lslot >= 0) st.flops_per_amp += 3.0 / (adjoint ? 2 : 1);   // per state (the adjoint sweeps two)
+            }
             st.nls = (int64_t)p.lsg.size() - st.ls0;
             prog.steps.push_back(st);
             ++prog.tile_passes;
@@ -398,6 +548,7 @@ struct Planner {
             rem.swap(nrem);
         }
         prog.slot_hi = (int64_t)p.slots.size();
+        prog.blk_lo = prog.blk_hi = (int64_t)p.blocks.size();
     }
 };
 
@@ -442,11 +593,14 @@ dq_status build_plan(dq_plan_s &p) {
 
     std::vector<int> order(G);
     for (int g = 0; g < G; ++g) order[g] = g;
+    const int dense_k = fused ? p.opt.dense_fuse : 0;
+    const bool dense = dense_k >= 4 && p.n >= dense_k + (p.dbl ? 4 : 5);
     // forward, all gates
     {
         Planner pl(p, false, p.R_fwd);
         pl.gslot_of = gslot;
-        pl.plan(p.fwd_full, order, true);
+        if (dense) pl.plan_dense(p.fwd_full, order, dense_k);
+        else pl.plan(p.fwd_full, order, true);
     }
     // forward from |0..0> with the leading one-qubit gates of every wire folded
     p.fold_off.assign(p.n, -1);
@@ -483,7 +637,8 @@ dq_status build_plan(dq_plan_s &p) {
             pl.gslot_of = gslot;
             const int64_t lo = (int64_t)p.slots.size() - (int64_t)std::count_if(p.fold_off.begin(), p.fold_off.end(),
                                                                                 [](int64_t o) { return o >= 0; });
-            pl.plan(p.fwd_fold, rest, true);
+            if (dense) pl.plan_dense(p.fwd_fold, rest, dense_k);
+            else pl.plan(p.fwd_fold, rest, true);
             p.fwd_fold.slot_lo = lo;
         }
     }
@@ -516,6 +671,7 @@ dq_status ensure_device(dq_plan_s &p, DevData **out) {
         return DQ_OK;
     }
     std::vector<char> blob;
+    const size_t o_b = put(blob, p.blocks), o_fa = put(blob, p.factors);
     const size_t o_g = put(blob, p.gates), o_f = put(blob, p.fixed), o_s = put(blob, p.slots),
                  o_o = put(blob, p.ops), o_l = put(blob, p.lsg), o_fo = put(blob, p.fold_off),
                  o_po = put(blob, p.poff), o_pg = put(blob, p.pg), o_pf = put(blob, p.pf),
@@ -533,6 +689,8 @@ dq_status ensure_device(dq_plan_s &p, DevData **out) {
     dd.gates = (DGate *)(b + o_g);
     dd.fixed = (double2 *)(b + o_f);
     dd.slots = (DSlot *)(b + o_s);
+    dd.blocks = (DBlock *)(b + o_b);
+    dd.factors = (int32_t *)(b + o_fa);
     dd.ops = (TOp *)(b + o_o);
     dd.lsg = (int32_t *)(b + o_l);
     dd.fold = (int64_t *)(b + o_fo);
@@ -623,11 +781,14 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
         switch (S.kind) {
         case ST_TILE: kind = lam ? DQ_PROF_ADJ_TILE : DQ_PROF_FWD_TILE; nl = 1; bytes = (lam ? 4 : 2) * SB; break;
         case ST_GRAD: kind = DQ_PROF_GRAD_GATE; nl = 1; bytes = 2 * SB; break;
+        case ST_DENSE: kind = DQ_PROF_DENSE; bytes = nst * 2 * SB; break;
         case ST_CNOT: bytes = nst * SB; break;
         case ST_CZ: bytes = nst * SB / 2; break;
         default: bytes = nst * 2 * SB; break;
         }
         ProfScope ps(p, kind, nl, bytes, s);
+        ps.flops = S.flops_per_amp * (double)batch * std::ldexp(1.0, p.n) * (lam ? 2 : 1);
+        if (S.kind == ST_GRAD) ps.flops = 3.0 * (double)batch * std::ldexp(1.0, p.n);
         switch (S.kind) {
         case ST_TILE: {
             TileArgs a{};
@@ -636,6 +797,8 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
             a.n = p.n;
             a.R = S.R;
             for (int i = 0; i < MAX_TILE_R; ++i) a.rbits[i] = S.rbits[i];
+            for (int i = 0; i < 3; ++i) a.lbits[i] = S.lbits[i];
+            for (int i = 0; i < MAX_TILE_R + 3; ++i) a.tbits[i] = S.tbits[i];
             a.batch = batch;
             a.ops = d.ops + S.op0;
             a.nops = (int32_t)S.nops;
@@ -660,6 +823,7 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
                 case ST_G1: e = launch_gate1(p.dbl, x, p.n, batch, S.bits[0], mats, mstride, S.slot, s); break;
                 case ST_CNOT: e = launch_cnot(p.dbl, x, p.n, batch, S.bits[0], S.bits[1], s); break;
                 case ST_CZ: e = launch_cz(p.dbl, x, p.n, batch, S.bits[0], S.bits[1], s); break;
+                case ST_DENSE: e = launch_dense(p.dbl, x, p.n, batch, S.k, S.bits, mats, mstride, S.slot, s); break;
                 default: e = launch_gatek(p.dbl, x, p.n, batch, S.k, S.bits, mats, mstride, S.slot, s); break;
                 }
             }
@@ -709,7 +873,8 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     dq_options o{1, 0, 1, 0};
     if (opt) o = *opt;
     if (o.tile_bits < 0 || o.tile_bits > 6) return fail(DQ_ERR_INVALID_ARG, "tile_bits %d outside 0..6", o.tile_bits);
-    if (o.dense_fuse != 0) return fail(DQ_ERR_UNSUPPORTED, "dense_fuse is not available in this build");
+    if (o.dense_fuse != 0 && o.dense_fuse != 4 && o.dense_fuse != 5)
+        return fail(DQ_ERR_INVALID_ARG, "dense_fuse must be 0, 4 or 5 (got %d)", o.dense_fuse);
     auto *p = new dq_plan_s();
     p->n = nqubits;
     p->dbl = dtype == DQ_C128;
@@ -806,7 +971,7 @@ dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) {
     const Program &f = plan->has_fold ? plan->fwd_fold : plan->fwd_full;
     s.fwd_steps = (int64_t)f.steps.size() + (plan->has_fold ? 1 : 0);
     s.fwd_tile_passes = f.tile_passes;
-    s.fwd_dense_blocks = 0;
+    s.fwd_dense_blocks = f.dense_steps;
     s.adj_steps = (int64_t)plan->adj.steps.size();
     s.folded_gates = plan->folded_gates;
     s.grad_gates = plan->ngrad;
@@ -921,6 +1086,10 @@ dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const doubl
     hipError_t e = launch_prepare(plan->dbl, d->gates, d->fixed, d->slots + prog.slot_lo,
                                   (int32_t)(prog.slot_hi - prog.slot_lo), params, params_bstride, data, data_bstride,
                                   mats, plan->block, bm, s);
+    if (e == hipSuccess)
+        e = launch_prepare_blocks(plan->dbl, d->gates, d->fixed, d->blocks + prog.blk_lo,
+                                  (int32_t)(prog.blk_hi - prog.blk_lo), d->factors, params, params_bstride, data,
+                                  data_bstride, mats, plan->block, bm, s);
     pp.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
     if (from_zero) {
@@ -1042,11 +1211,333 @@ dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset) {
         plan->acc.launches[r.kind] += r.nl;
         plan->acc.ms[r.kind] += ms;
         plan->acc.bytes[r.kind] += r.bytes;
+        plan->acc.flops[r.kind] += r.flops;
     }
     plan->precs.clear();
     plan->evused = 0;
     *out = plan->acc;
     if (reset) plan->acc = dq_profile{};
+    return ok();
+}
+
+// ================================================================ uneven batches
+}  // extern "C"
+
+struct dq_multi_s {
+    int dbl = 0;
+    int R_fwd = 0, R_adj = 0;
+    std::vector<dq_plan> plans;
+    std::vector<dq_obs> obs;
+    std::vector<int64_t> st_off, par_off, out_off;
+    int64_t st_total = 0, par_total = 0, out_total = 0;
+    std::vector<size_t> ws_off;
+    std::vector<WsLayout> lay;
+    size_t ws_total = 0;
+    std::vector<char> batched;
+    // host entries: depth-major, circuits in order; ops / lsg hold the
+    // element index into the plan tables until the device upload resolves them
+    std::vector<std::vector<MultiEntry>> fwd, adj;
+    std::vector<std::vector<int>> fwd_c, adj_c;       // circuit of each entry
+    std::vector<int64_t> fwd_units, adj_units;
+    std::vector<int32_t> adj_maxnls;
+    std::mutex mu;
+    struct Dev {
+        void *blob = nullptr;
+        std::vector<MultiEntry *> fwd, adj;
+    };
+    std::map<int, Dev> dev;
+};
+
+namespace {
+
+bool tile_only(const Program &p, int R) {
+    for (const Step &s : p.steps)
+        if (s.kind != ST_TILE || s.R != R) return false;
+    return true;
+}
+
+MultiEntry make_entry(const Step &S, int n) {
+    MultiEntry E{};
+    E.n = n;
+    E.nops = (int32_t)S.nops;
+    E.nls = (int32_t)S.nls;
+    E.ops = reinterpret_cast<const TOp *>((intptr_t)S.op0);
+    E.lsg = reinterpret_cast<const int32_t *>((intptr_t)S.ls0);
+    for (int k = 0; k < MAX_TILE_R; ++k) E.rbits[k] = S.rbits[k];
+    for (int k = 0; k < 3; ++k) E.lbits[k] = S.lbits[k];
+    for (int k = 0; k < MAX_TILE_R + 3; ++k) E.tbits[k] = S.tbits[k];
+    return E;
+}
+
+dq_status ensure_multi(dq_multi_s &m, dq_multi_s::Dev **out) {
+    int dev = 0;
+    DQ_HIP(hipGetDevice(&dev));
+    for (dq_plan p : m.plans) {
+        DevData *d = nullptr;
+        dq_status st = ensure_device(*p, &d);
+        if (st != DQ_OK) return st;
+    }
+    std::lock_guard<std::mutex> lk(m.mu);
+    auto it = m.dev.find(dev);
+    if (it != m.dev.end()) {
+        *out = &it->second;
+        return DQ_OK;
+    }
+    std::vector<MultiEntry> all;
+    std::vector<size_t> fstart, astart;
+    auto resolve = [&](const std::vector<MultiEntry> &v, const std::vector<int> &cs) {
+        for (size_t i = 0; i < v.size(); ++i) {
+            MultiEntry E = v[i];
+            DevData &d = m.plans[cs[i]]->dev[dev];
+            E.ops = d.ops + (intptr_t)E.ops;
+            E.lsg = d.lsg + (intptr_t)E.lsg;
+            all.push_back(E);
+        }
+    };
+    for (size_t k = 0; k < m.fwd.size(); ++k) {
+        fstart.push_back(all.size());
+        resolve(m.fwd[k], m.fwd_c[k]);
+    }
+    for (size_t k = 0; k < m.adj.size(); ++k) {
+        astart.push_back(all.size());
+        resolve(m.adj[k], m.adj_c[k]);
+    }
+    dq_multi_s::Dev D;
+    DQ_HIP(hipMalloc(&D.blob, std::max<size_t>(all.size(), 1) * sizeof(MultiEntry)));
+    hipError_t e = hipMemcpy(D.blob, all.data(), all.size() * sizeof(MultiEntry), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(D.blob);
+        return fail(DQ_ERR_HIP, "multi upload: %s", hipGetErrorString(e));
+    }
+    for (size_t k : fstart) D.fwd.push_back((MultiEntry *)D.blob + k);
+    for (size_t k : astart) D.adj.push_back((MultiEntry *)D.blob + k);
+    *out = &(m.dev[dev] = D);
+    return DQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs, int32_t nplans) {
+    if (!out || !plans || !obs || nplans < 1) return fail(DQ_ERR_INVALID_ARG, "need plans, observables and nplans >= 1");
+    *out = nullptr;
+    auto *m = new dq_multi_s();
+    m->dbl = plans[0] ? plans[0]->dbl : 0;
+    for (int c = 0; c < nplans; ++c) {
+        if (!plans[c] || !obs[c]) {
+            delete m;
+            return fail(DQ_ERR_INVALID_ARG, "circuit %d: NULL plan or observable", c);
+        }
+        if (plans[c]->dbl != m->dbl) {
+            delete m;
+            return fail(DQ_ERR_INVALID_ARG, "circuit %d: dtype differs from circuit 0", c);
+        }
+        if (plans[c]->ndata > 0) {
+            delete m;
+            return fail(DQ_ERR_UNSUPPORTED, "circuit %d: data-encoded gates are not supported in a multi-plan", c);
+        }
+        if (obs[c]->n != plans[c]->n) {
+            delete m;
+            return fail(DQ_ERR_INVALID_ARG, "circuit %d: observable for %d qubits, plan for %d", c, obs[c]->n, plans[c]->n);
+        }
+        m->plans.push_back(plans[c]);
+        m->obs.push_back(obs[c]);
+    }
+    // common tile shape: that of the first fused plan
+    for (dq_plan p : m->plans)
+        if (p->R_fwd > 0) {
+            m->R_fwd = p->R_fwd;
+            m->R_adj = p->R_adj;
+            break;
+        }
+    const size_t amp = m->dbl ? 16 : 8;
+    for (int c = 0; c < nplans; ++c) {
+        dq_plan p = m->plans[c];
+        m->st_off.push_back(m->st_total);
+        m->st_total += (int64_t)(align256(((size_t)1 << p->n) * amp) / amp);
+        m->par_off.push_back(m->par_total);
+        m->par_total += p->nparams;
+        m->out_off.push_back(m->out_total);
+        m->out_total += m->obs[c]->nobs;
+        const WsLayout L = layout(*p, m->obs[c], 1, 0, 1);
+        m->ws_off.push_back(m->ws_total);
+        m->lay.push_back(L);
+        m->ws_total += align256(L.total);
+        const Program &f = p->has_fold ? p->fwd_fold : p->fwd_full;
+        m->batched.push_back(p->R_fwd > 0 && p->R_fwd == m->R_fwd && p->R_adj == m->R_adj && tile_only(f, m->R_fwd) &&
+                             tile_only(p->adj, m->R_adj));
+    }
+    // depth tables
+    for (int pass = 0; pass < 2; ++pass) {
+        auto &tab = pass ? m->adj : m->fwd;
+        auto &tabc = pass ? m->adj_c : m->fwd_c;
+        auto &units = pass ? m->adj_units : m->fwd_units;
+        for (int c = 0; c < nplans; ++c) {
+            if (!m->batched[c]) continue;
+            dq_plan p = m->plans[c];
+            const Program &prog = pass ? p->adj : (p->has_fold ? p->fwd_fold : p->fwd_full);
+            for (size_t d = 0; d < prog.steps.size(); ++d) {
+                if (tab.size() <= d) {
+                    tab.resize(d + 1);
+                    tabc.resize(d + 1);
+                    units.resize(d + 1, 0);
+                    if (pass) m->adj_maxnls.resize(d + 1, 0);
+                }
+                MultiEntry E = make_entry(prog.steps[d], p->n);
+                const WsLayout &L = m->lay[c];
+                E.st_off = m->st_off[c];
+                E.mats_off = (int64_t)(m->ws_off[c] + L.mats);
+                E.lam_off = (int64_t)(m->ws_off[c] + L.lam);
+                E.part_off = (int64_t)(m->ws_off[c] + L.part);
+                E.ngrad = p->ngrad;
+                const int64_t tiles = int64_t(1) << (p->n - 6 - (pass ? m->R_adj : m->R_fwd));
+                E.wps = (int32_t)(pass ? grad_waves(*p, 1) : 1);
+                E.unit_begin = units[d];
+                units[d] += pass ? E.wps : tiles;
+                if (pass) m->adj_maxnls[d] = std::max<int32_t>(m->adj_maxnls[d], E.nls);
+                tab[d].push_back(E);
+                tabc[d].push_back(c);
+            }
+        }
+    }
+    *out = m;
+    return ok();
+}
+
+void dq_multi_destroy(dq_multi m) {
+    if (!m) return;
+    for (auto &kv : m->dev) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess) {
+            (void)hipSetDevice(kv.first);
+            (void)hipFree(kv.second.blob);
+            (void)hipSetDevice(cur);
+        }
+    }
+    delete m;
+}
+
+dq_status dq_multi_layout(dq_multi m, int64_t *state_amps, int64_t *param_count, int64_t *nout, int64_t *state_off,
+                          int64_t *param_off, int64_t *out_off) {
+    if (!m) return fail(DQ_ERR_INVALID_ARG, "NULL multi-plan");
+    if (state_amps) *state_amps = m->st_total;
+    if (param_count) *param_count = m->par_total;
+    if (nout) *nout = m->out_total;
+    for (size_t c = 0; c < m->plans.size(); ++c) {
+        if (state_off) state_off[c] = m->st_off[c];
+        if (param_off) param_off[c] = m->par_off[c];
+        if (out_off) out_off[c] = m->out_off[c];
+    }
+    return ok();
+}
+
+dq_status dq_multi_workspace_size(dq_multi m, size_t *bytes) {
+    if (!m || !bytes) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    *bytes = m->ws_total;
+    return ok();
+}
+
+dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *ws, size_t ws_bytes, void *stream) {
+    if (!m || !states) return fail(DQ_ERR_INVALID_ARG, "NULL multi-plan or states");
+    if (m->par_total > 0 && !params) return fail(DQ_ERR_INVALID_ARG, "params is NULL");
+    if (!ws || ws_bytes < m->ws_total) return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed", m->ws_total);
+    dq_multi_s::Dev *D = nullptr;
+    dq_status st = ensure_multi(*m, &D);
+    if (st != DQ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t amp = m->dbl ? 16 : 8;
+    char *w = (char *)ws;
+    for (size_t c = 0; c < m->plans.size(); ++c) {
+        dq_plan p = m->plans[c];
+        void *sc = (char *)states + m->st_off[c] * amp;
+        const double *pc = params ? params + m->par_off[c] : nullptr;
+        if (!m->batched[c]) {
+            if ((st = dq_apply_circuit(p, sc, 1, pc, 0, nullptr, 0, 1, w + m->ws_off[c], m->lay[c].total, stream)) != DQ_OK)
+                return st;
+            continue;
+        }
+        DevData &d = p->dev.at([&] { int dv = 0; (void)hipGetDevice(&dv); return dv; }());
+        const Program &prog = p->has_fold ? p->fwd_fold : p->fwd_full;
+        void *mats = w + m->ws_off[c] + m->lay[c].mats;
+        hipError_t e = launch_prepare(p->dbl, d.gates, d.fixed, d.slots + prog.slot_lo, (int32_t)(prog.slot_hi - prog.slot_lo),
+                                      pc, 0, nullptr, 0, mats, p->block, 1, s);
+        if (e == hipSuccess)
+            e = p->has_fold ? launch_init_product(p->dbl, sc, p->n, 1, mats, 0, d.fold, s)
+                            : launch_init_zero(p->dbl, sc, p->n, 1, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi init: %s", hipGetErrorString(e));
+    }
+    for (size_t k = 0; k < m->fwd.size(); ++k) {
+        hipError_t e = launch_tile_fwd_multi(m->dbl, m->R_fwd, states, ws, D->fwd[k], (int32_t)m->fwd[k].size(),
+                                             m->fwd_units[k], s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi tile pass: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
+dq_status dq_multi_expval(dq_multi m, const void *states, double *out, void *ws, size_t ws_bytes, void *stream) {
+    if (!m || !states || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (!ws || ws_bytes < m->ws_total) return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed", m->ws_total);
+    const size_t amp = m->dbl ? 16 : 8;
+    for (size_t c = 0; c < m->plans.size(); ++c) {
+        dq_status st = dq_expval(m->plans[c], m->obs[c], (const char *)states + m->st_off[c] * amp, 1,
+                                 out + m->out_off[c], (char *)ws + m->ws_off[c], m->lay[c].total, stream);
+        if (st != DQ_OK) return st;
+    }
+    return ok();
+}
+
+dq_status dq_multi_adjoint_grad(dq_multi m, void *states, const double *params, const double *grad_out,
+                                double *grad_params, void *ws, size_t ws_bytes, void *stream) {
+    if (!m || !states || !grad_out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (m->par_total > 0 && (!params || !grad_params)) return fail(DQ_ERR_INVALID_ARG, "params / grad_params is NULL");
+    if (!ws || ws_bytes < m->ws_total) return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed", m->ws_total);
+    dq_multi_s::Dev *D = nullptr;
+    dq_status st = ensure_multi(*m, &D);
+    if (st != DQ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t amp = m->dbl ? 16 : 8;
+    char *w = (char *)ws;
+    int dv = 0;
+    DQ_HIP(hipGetDevice(&dv));
+    for (size_t c = 0; c < m->plans.size(); ++c) {
+        dq_plan p = m->plans[c];
+        void *sc = (char *)states + m->st_off[c] * amp;
+        const double *pc = params ? params + m->par_off[c] : nullptr;
+        double *gc = grad_params ? grad_params + m->par_off[c] : nullptr;
+        if (!m->batched[c]) {
+            if ((st = dq_adjoint_grad(p, m->obs[c], sc, 1, pc, 0, nullptr, 0, grad_out + m->out_off[c], gc, nullptr, 0,
+                                      w + m->ws_off[c], m->lay[c].total, stream)) != DQ_OK)
+                return st;
+            continue;
+        }
+        DevData &d = p->dev.at(dv);
+        const DGroup *g = nullptr;
+        const DTerm *t = nullptr;
+        if ((st = ensure_obs(*m->obs[c], &g, &t)) != DQ_OK) return st;
+        void *mats = w + m->ws_off[c] + m->lay[c].mats;
+        void *lam = w + m->ws_off[c] + m->lay[c].lam;
+        hipError_t e = launch_prepare(p->dbl, d.gates, d.fixed, d.slots + p->adj.slot_lo,
+                                      (int32_t)(p->adj.slot_hi - p->adj.slot_lo), pc, 0, nullptr, 0, mats, p->block, 1, s);
+        if (e == hipSuccess)
+            e = launch_lambda(p->dbl, sc, lam, p->n, 1, g, (int32_t)m->obs[c]->groups.size(), t, grad_out + m->out_off[c],
+                              m->obs[c]->nobs, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi adjoint seed: %s", hipGetErrorString(e));
+    }
+    for (size_t k = 0; k < m->adj.size(); ++k) {
+        hipError_t e = launch_tile_adj_multi(m->dbl, m->R_adj, states, ws, D->adj[k], (int32_t)m->adj[k].size(),
+                                             m->adj_units[k], m->adj_maxnls[k], s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi adjoint pass: %s", hipGetErrorString(e));
+    }
+    for (size_t c = 0; c < m->plans.size(); ++c) {
+        dq_plan p = m->plans[c];
+        if (!m->batched[c] || p->nparams == 0) continue;
+        DevData &d = p->dev.at(dv);
+        double *partial = (double *)(w + m->ws_off[c] + m->lay[c].part);
+        hipError_t e = launch_grad_final(partial, 1, (int32_t)grad_waves(*p, 1), p->ngrad, d.poff, d.pg, d.pf, p->nparams,
+                                         0, grad_params + m->par_off[c], s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi grad reduce: %s", hipGetErrorString(e));
+    }
     return ok();
 }
 

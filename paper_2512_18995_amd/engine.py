@@ -30,14 +30,14 @@ class Plan:
     its first use on a device)."""
 
     def __init__(self, circuit, dtype: str = "c64", fusion: bool = True, tile_bits: int = 0,
-                 fold_init: bool = True):
+                 fold_init: bool = True, dense_fuse: int = 0):
         self.n = int(circuit.n)
         self.dtype = dtype
         self.nparams = int(circuit.n_params)
         self.ndata = int(circuit.n_data)
         self.gates = list(circuit.gates)
         arr, keep = _lib.gate_array(self.gates)
-        opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, 0)
+        opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, int(dense_fuse))
         h = ctypes.c_void_p()
         check(lib().dq_plan_create(ctypes.byref(h), self.n, arr, len(self.gates), self.nparams, self.ndata,
                                    _lib.C64 if dtype == "c64" else _lib.C128, ctypes.byref(opt)), "dq_plan_create")
@@ -70,7 +70,7 @@ class Plan:
         """{family: {"launches", "ms", "bytes"}} summed since the last reset."""
         p = _lib.DqProfile()
         check(lib().dq_profile_read(self._h, ctypes.byref(p), 1 if reset else 0), "dq_profile_read")
-        return {k: {"launches": p.launches[i], "ms": p.ms[i], "bytes": p.bytes[i]}
+        return {k: {"launches": p.launches[i], "ms": p.ms[i], "bytes": p.bytes[i], "flops": p.flops[i]}
                 for i, k in enumerate(_lib.PROF_KINDS)}
 
     def workspace_size(self, batch: int, per_sample: bool = False, grad: int = 0, obs: "Observable" = None) -> int:
@@ -225,3 +225,153 @@ def expectation(plan: Plan, obs: Observable, params, data=None, batch: Optional[
         batch = data.shape[0] if data is not None and data.dim() == 2 else (
             params.shape[0] if params is not None and params.dim() == 2 else 1)
     return ExpvalFunction.apply(params, data, plan, obs, batch)
+
+
+# ---------------------------------------------------------------- uneven batches
+class Multi:
+    """Several circuits of different sizes run together (one tile launch per
+    pass depth across all circuits).  States and parameters are packed: use
+    ``states()``, ``pack_params()`` and the offsets."""
+
+    def __init__(self, plans: Sequence[Plan], observables: Sequence[Observable]):
+        self.plans, self.obs = list(plans), list(observables)
+        n = len(self.plans)
+        ph = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
+        oh = (ctypes.c_void_p * n)(*[o.handle.value for o in self.obs])
+        h = ctypes.c_void_p()
+        check(lib().dq_multi_create(ctypes.byref(h), ph, oh, n), "dq_multi_create")
+        self._h = h
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        so, po, oo = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+        check(lib().dq_multi_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), so, po, oo), "dq_multi_layout")
+        self.state_amps, self.param_count, self.nout = a.value, b.value, c.value
+        self.state_off, self.param_off, self.out_off = list(so), list(po), list(oo)
+        sz = ctypes.c_size_t()
+        check(lib().dq_multi_workspace_size(h, ctypes.byref(sz)), "dq_multi_workspace_size")
+        self.ws_bytes = sz.value
+        self.dtype = self.plans[0].dtype
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().dq_multi_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def states(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.state_amps, dtype=CDTYPE[self.dtype], device=device)
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        return torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+
+    def pack_params(self, per_circuit, device="cuda") -> torch.Tensor:
+        out = torch.zeros(max(self.param_count, 1), dtype=torch.float64, device=device)
+        for off, p in zip(self.param_off, per_circuit):
+            p = torch.as_tensor(p, dtype=torch.float64, device=device).reshape(-1)
+            out[off:off + p.numel()] = p
+        return out
+
+    def state_of(self, states: torch.Tensor, c: int) -> torch.Tensor:
+        return states[self.state_off[c]:self.state_off[c] + (1 << self.plans[c].n)]
+
+    def apply(self, states, params, ws):
+        check(lib().dq_multi_apply(self._h, states.data_ptr(), params.data_ptr(), ws.data_ptr(), ws.numel(),
+                                   _stream(states.device)), "dq_multi_apply")
+
+    def expval(self, states, ws, out=None):
+        if out is None:
+            out = torch.empty(self.nout, dtype=torch.float64, device=states.device)
+        check(lib().dq_multi_expval(self._h, states.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream(states.device)), "dq_multi_expval")
+        return out
+
+    def adjoint_grad(self, states, params, grad_out, ws, grad=None):
+        if grad is None:
+            grad = torch.empty_like(params)
+        check(lib().dq_multi_adjoint_grad(self._h, states.data_ptr(), params.data_ptr(), grad_out.data_ptr(),
+                                          grad.data_ptr(), ws.data_ptr(), ws.numel(), _stream(states.device)),
+              "dq_multi_adjoint_grad")
+        return grad
+
+
+# ---------------------------------------------------------------- autotuner
+def _structure_key(circuit, dtype: str, batch: int, per_sample: bool, grad: bool, device) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    h.update(("%d|%s|%d|%d|%d|" % (circuit.n, dtype, batch, per_sample, grad)).encode())
+    for g in circuit.gates:
+        h.update(("%s:%s:%s;" % (g.op, ",".join(map(str, g.wires)), g.src)).encode())
+    props = torch.cuda.get_device_properties(device)
+    h.update(getattr(props, "gcnArchName", props.name).encode())
+    return h.hexdigest()[:24]
+
+
+def candidate_options(dtype: str, n: int):
+    """Fusion width / tile shape candidates: register bits per tile and the
+    dense-block width of the forward sweep."""
+    tiles = [r for r in ((3, 4, 5) if dtype == "c64" else (3, 4)) if r <= n - 6] or [0]
+    out = [{"tile_bits": r, "dense_fuse": 0} for r in tiles]
+    if dtype == "c64":
+        out += [{"tile_bits": tiles[-1], "dense_fuse": k} for k in (4, 5) if n >= k + 5]
+    return out
+
+
+def autotune(circuit, dtype, obs: Observable, params, data=None, batch: int = 1, grad: bool = True,
+             reps: int = 2, cache_path: Optional[str] = None, device="cuda:0", verbose: bool = False) -> dict:
+    """Pick the plan options (tile bits, dense-fusion width) with the lowest
+    measured time of one forward (+ adjoint) step on this device; results are
+    cached in a JSON file keyed by circuit structure, dtype, batch and GPU
+    architecture (DQ_AUTOTUNE_CACHE, default ~/.cache/dq_autotune.json)."""
+    import json
+    import os
+    path = cache_path or os.environ.get("DQ_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/dq_autotune.json"))
+    p = _f64(params, device) if params is not None else None
+    d = _f64(data, device) if data is not None else None
+    per_sample = _stride(p) != 0 or _stride(d) != 0
+    key = _structure_key(circuit, dtype, batch, per_sample, grad, device)
+    cache = {}
+    if os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        return cache[key]
+    gout = torch.ones((batch, obs.nobs), dtype=torch.float64, device=device)
+    best, timings = None, []
+    for opt in candidate_options(dtype, circuit.n):
+        plan = Plan(circuit, dtype, tile_bits=opt["tile_bits"], dense_fuse=opt["dense_fuse"])
+        st = plan.state(batch, device)
+        ws = plan.workspace(batch, per_sample, 1 if grad else 0, obs, device)
+
+        def step():
+            apply_circuit(plan, st, p, d, from_zero=True, ws=ws)
+            expval(plan, obs, st, ws=ws)
+            if grad:
+                adjoint_grad(plan, obs, st, p, d, gout, ws=ws, want_data=False)
+
+        step()
+        torch.cuda.synchronize(device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize(device)
+        ms = e0.elapsed_time(e1) / reps
+        timings.append(dict(opt, ms=ms))
+        if verbose:
+            print("autotune", opt, "%.3f ms" % ms, flush=True)
+        if best is None or ms < best["ms"]:
+            best = dict(opt, ms=ms)
+        del plan, st, ws
+    result = {"tile_bits": best["tile_bits"], "dense_fuse": best["dense_fuse"], "ms": best["ms"], "tried": timings}
+    cache[key] = result
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        json.dump(cache, open(path, "w"), indent=1)
+    except OSError:
+        pass
+    return result

@@ -200,3 +200,136 @@ def test_norm_preserved_deep_c64():
     _, st = gpu_forward(c, params, None, B, "c64", True)
     norms = torch.linalg.vector_norm(st.to(torch.complex128), dim=1).cpu().numpy()
     assert np.all(np.abs(norms - 1) < 1e-5), norms
+
+
+# ------------------------------------------------------------------ matrix-core dense blocks
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("k", [4, 5])
+def test_dense_unitary_on_matrix_cores(dtype, k):
+    """A dense 4- or 5-qubit unitary in a fused plan runs as one MFMA sweep;
+    target bits low, high, mixed and unordered."""
+    rng = np.random.default_rng(600 + k)
+    n = 13
+    x = rand_state(rng, n)
+    placements = [tuple(range(n - k, n)), tuple(range(k)), tuple(range(k))[::-1],
+                  tuple(int(w) for w in rng.choice(n, size=k, replace=False)),
+                  tuple(int(w) for w in rng.choice(n, size=k, replace=False))]
+    for wires in placements:
+        c = W.Circuit(n, [W.Gate("unitary", wires, matrix=W.random_unitary(rng, k))])
+        plan, st = gpu_forward(c, None, None, 1, dtype, True, init=x)
+        assert plan.stats()["fwd_dense_blocks"] == 1
+        assert_state(st.cpu().numpy()[0], oracle.state(c, psi0=x), dtype, 2, "dense unitary %s" % (wires,))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("k", [4, 5])
+@pytest.mark.parametrize("n,batch,per_sample", [(11, 2, False), (14, 3, True)])
+def test_dense_fuse_forward_and_adjoint(dtype, k, n, batch, per_sample):
+    """Forward sweep fused into dense k-qubit blocks (matrix cores), adjoint
+    through register tiles: states, expectations and gradients vs the oracle."""
+    rng = np.random.default_rng(700 + n + k)
+    ops = ("h", "x", "y", "rx", "ry", "rz", "cnot", "cz", "swap", "cp", "rzz")
+    c = W.random_circuit(rng, n, 10 * n, ops=ops, with_data=True)
+    params, data = W.random_params(rng, c, batch, per_sample)
+    obs = [W.random_pauli_sum(rng, n, 4)]
+    from gpu_helpers import DEV as _dev
+    plan = dq.Plan(c, dtype, dense_fuse=k)
+    assert plan.stats()["fwd_dense_blocks"] > 0
+    st = plan.state(batch, _dev)
+    dq.apply_circuit(plan, st, t64(params), t64(data), from_zero=True)
+    got = st.cpu().numpy()
+    for b in range(batch):
+        assert_state(got[b], oracle.state(c, params, data, b), dtype, len(c.gates), "dense-fused sample %d" % b)
+    O = dq.Observable(n, obs)
+    w = rng.standard_normal((batch, 1))
+    gp, gd = dq.adjoint_grad(plan, O, st, t64(params), t64(data), t64(w))
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w, batch, threads=8)
+    normwise(gp.cpu().numpy(), rp, RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12, "d/dparams")
+    normwise(gd.cpu().numpy(), rd, RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12, "d/ddata")
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_dense_fuse_hea_family(k):
+    """The 32-qubit workload's circuit family at 16 qubits: dense-fused forward
+    equals the tiled forward and the oracle."""
+    wl = W.config(5, n=16, layers=4)
+    c = wl.circuit
+    a = gpu_forward(c, wl.params, None, 1, "c64", True)[1].cpu().numpy()[0]
+    plan = dq.Plan(c, "c64", dense_fuse=k)
+    st = plan.state(1, DEV)
+    dq.apply_circuit(plan, st, t64(wl.params), None, from_zero=True)
+    b = st.cpu().numpy()[0]
+    want = oracle.state(c, wl.params)
+    assert_state(a, want, "c64", len(c.gates), "tiles")
+    assert_state(b, want, "c64", len(c.gates), "dense blocks")
+
+
+# ------------------------------------------------------------------ uneven batches
+def _uneven(count=6, nmin=7, nmax=12, lmin=2, lmax=5):
+    return W.config(4, count=count, nmin=nmin, nmax=nmax, lmin=lmin, lmax=lmax)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_multi_plan_matches_oracle(dtype):
+    """Circuits of uneven size in one multi-plan: every circuit's state,
+    expectation and gradient equal the oracle's (and the single-plan path)."""
+    mw = _uneven()
+    plans = [dq.Plan(it.circuit, dtype) for it in mw.items]
+    obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
+    M = dq.Multi(plans, obs)
+    st = M.states(DEV)
+    ws = M.workspace(DEV)
+    params = M.pack_params([it.params for it in mw.items], DEV)
+    M.apply(st, params, ws)
+    E = M.expval(st, ws).cpu().numpy()
+    got = st.cpu().numpy()
+    for c, it in enumerate(mw.items):
+        want = oracle.state(it.circuit, it.params)
+        assert_state(M.state_of(torch.as_tensor(got), c).numpy(), want, dtype, len(it.circuit.gates), "circuit %d" % c)
+        normwise([E[M.out_off[c]]], oracle.expvals(it.circuit.n, want, it.observables), RTOL[dtype],
+                 1e-6 if dtype == "c64" else 1e-12, "expval %d" % c)
+    w = torch.as_tensor(np.random.default_rng(3).standard_normal(M.nout), device=DEV)
+    g = M.adjoint_grad(st, params, w, ws).cpu().numpy()
+    for c, it in enumerate(mw.items):
+        rp, _ = oracle.grad_param_shift(it.circuit, it.params, None, it.observables,
+                                        np.array([[float(w[M.out_off[c]])]]), 1, threads=8)
+        normwise(g[M.param_off[c]:M.param_off[c] + it.circuit.n_params], rp, RTOL[dtype],
+                 1e-6 if dtype == "c64" else 1e-12, "gradient %d" % c)
+
+
+def test_multi_plan_graph_replay():
+    """The multi-plan step captured in a HIP graph: several replays with eager
+    work in between each equal the eager result."""
+    mw = _uneven(count=5, nmin=8, nmax=13)
+    plans = [dq.Plan(it.circuit, "c64") for it in mw.items]
+    obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
+    M = dq.Multi(plans, obs)
+    st, ws = M.states(DEV), M.workspace(DEV)
+    params = M.pack_params([it.params for it in mw.items], DEV)
+    w = torch.ones(M.nout, dtype=torch.float64, device=DEV)
+    E, G = torch.empty(M.nout, dtype=torch.float64, device=DEV), torch.empty_like(params)
+
+    def step():
+        M.apply(st, params, ws)
+        M.expval(st, ws, E)
+        M.adjoint_grad(st, params, w, ws, G)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()                       # warm-up: plan tables uploaded outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ref_E, ref_G = E.clone(), G.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for r in range(3):
+        E.zero_()
+        G.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(E, ref_E) and torch.equal(G, ref_G), "replay %d differs" % r
+        step()                       # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(E, ref_E)

@@ -116,7 +116,7 @@ def sweeps(args):
             cases.append(("unitary", tuple(range(0, k))))
         for fusion in (False, True):
             for op, wires in cases:
-                if fusion and op == "unitary":
+                if fusion and op == "unitary" and len(wires) < 4:
                     continue
                 src = "param" if op in W.ROTATIONS else "none"
                 g = W.Gate(op, wires, src, 0 if src == "param" else -1,
@@ -133,14 +133,15 @@ def sweeps(args):
                     dq.apply_circuit(plan, st, p, None, from_zero=False, ws=ws)
                 torch.cuda.synchronize()
                 pr = plan.profile_read(reset=True)
-                fam = "fwd_tile" if fusion else "gate"
+                fam = ("dense" if op == "unitary" else "fwd_tile") if fusion else "gate"
                 v = pr[fam]
                 if not v["launches"]:
                     continue
                 ms = v["ms"] / v["launches"]
                 gbs = (v["bytes"] / v["launches"] / 1e9) / (ms / 1e3)
                 row = {"dtype": dtype, "n": n, "op": op, "wires": list(wires),
-                       "phys_bits": [n - 1 - w for w in wires], "path": "tile" if fusion else "plain",
+                       "phys_bits": [n - 1 - w for w in wires],
+                       "path": ("mfma" if fam == "dense" else "tile") if fusion else "plain",
                        "ms": ms, "GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
                        "bytes": v["bytes"] / v["launches"]}
                 rows.append(row)
@@ -163,12 +164,71 @@ def sweeps(args):
           flush=True)
 
 
+def bench_uneven(args):
+    """64 circuits of uneven size (12..22 qubits, 4..16 layers) in one
+    multi-plan: forward, expectation and adjoint gradient of every circuit per
+    step, eager and replayed from a captured HIP graph."""
+    import numpy as np
+    import torch
+    import paper_2512_18995_amd as dq
+    import workloads as W
+    dev = "cuda:0"
+    mw = W.config(4)
+    plans = [dq.Plan(it.circuit, "c64") for it in mw.items]
+    obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
+    M = dq.Multi(plans, obs)
+    st, ws = M.states(dev), M.workspace(dev)
+    params = M.pack_params([it.params for it in mw.items], dev)
+    w = torch.ones(M.nout, dtype=torch.float64, device=dev)
+    E, G = torch.empty(M.nout, dtype=torch.float64, device=dev), torch.empty_like(params)
+
+    def step():
+        M.apply(st, params, ws)
+        M.expval(st, ws, E)
+        M.adjoint_grad(st, params, w, ws, G)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(max(args.warmup, 1)):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / args.steps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / args.steps
+    amps = sum(1 << it.circuit.n for it in mw.items)
+    out = {"metric": METRIC, "value": len(mw.items) / graph, "unit": "circuits/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": graph * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+           "config": {"workload": mw.name, "circuits": len(mw.items),
+                      "qubits": [it.circuit.n for it in mw.items], "gates": sum(len(it.circuit.gates) for it in mw.items),
+                      "params": M.param_count, "amplitudes": amps, "grad": "adjoint", "seed": mw.seed,
+                      "parallelism": "none (one GPU)"},
+           "eager_ms_per_step": eager * 1e3, "graph_speedup": eager / graph,
+           "checks": {"E_abs_sum": float(E.abs().sum().item()), "grad_norm": float(torch.linalg.vector_norm(G).item())},
+           "roofline": None, "cpu_baseline": None, "source_hash": kernel_source_hash()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg5", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--workload", default="cfg5", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--dense-fuse", type=int, default=0, choices=[0, 4, 5],
                     help="forward sweep as fused dense k-qubit blocks on the matrix cores")
@@ -198,6 +258,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sweeps:
         sweeps(args)
+        return
+    if args.workload == "cfg4":
+        bench_uneven(args)
         return
     cid = int(args.workload[3:])
     wl = W.config(cid)

@@ -251,6 +251,10 @@ void dq_multi_destroy(dq_multi m);
 dq_status dq_multi_layout(dq_multi m, int64_t *state_amps, int64_t *param_count, int64_t *nout,
                           int64_t *state_off, int64_t *param_off, int64_t *out_off);
 dq_status dq_multi_workspace_size(dq_multi m, size_t *bytes);
+/* batched[c] (nplans entries, caller-owned) = 1 if circuit c runs inside the
+ * shared tile launches, 0 if it takes the single-plan path; *count (nullable)
+ * = number of batched circuits.  Host only, no device work. */
+dq_status dq_multi_batched(dq_multi m, int32_t *batched, int32_t *count);
 /* every circuit from |0...0> (leading one-qubit gates folded) */
 dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *ws, size_t ws_bytes, void *stream);
 /* out[out_off[c] + o] = expectation of observable o of circuit c (float64, device) */

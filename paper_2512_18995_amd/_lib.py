@@ -24,7 +24,7 @@ EXPORTS = ["dq_plan_create", "dq_plan_destroy", "dq_plan_get_stats", "dq_obs_cre
            "dq_workspace_size", "dq_state_init", "dq_apply_circuit", "dq_expval", "dq_adjoint_grad",
            "dq_last_error", "dq_version", "dq_profile_enable", "dq_profile_read",
            "dq_multi_create", "dq_multi_destroy", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
-           "dq_multi_expval", "dq_multi_adjoint_grad"]
+           "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched"]
 PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other", "dense"]
 
 
@@ -90,6 +90,7 @@ def lib():
         i64p = POINTER(c_int64)
         L.dq_multi_layout.argtypes = [vp, i64p, i64p, i64p, i64p, i64p, i64p]
         L.dq_multi_workspace_size.argtypes = [vp, POINTER(c_size_t)]
+        L.dq_multi_batched.argtypes = [vp, POINTER(c_int32), POINTER(c_int32)]
         L.dq_multi_apply.argtypes = [vp, vp, vp, vp, c_size_t, vp]
         L.dq_multi_expval.argtypes = [vp, vp, vp, vp, c_size_t, vp]
         L.dq_multi_adjoint_grad.argtypes = [vp, vp, vp, vp, vp, vp, c_size_t, vp]
@@ -98,7 +99,7 @@ def lib():
         for f in ("dq_plan_create", "dq_plan_get_stats", "dq_obs_create", "dq_workspace_size", "dq_state_init",
                   "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read",
                   "dq_multi_create", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
-                  "dq_multi_expval", "dq_multi_adjoint_grad"):
+                  "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib

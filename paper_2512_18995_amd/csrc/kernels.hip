@@ -320,19 +320,38 @@ __global__ __launch_bounds__(256) void k_init_product(cx<T> *st, int n, const cx
 }
 
 // ============================================================ plain per-gate sweeps
+// Each thread keeps SWEEP_U pairs in flight: all loads are issued before the
+// first update, so a wave has 2 x SWEEP_U independent 512-byte (complex64)
+// requests outstanding.
+constexpr int SWEEP_U = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gate1(cx<T> *st, int n, int64_t total, int bit, const cx<T> *mats,
                                                int64_t mstride, int64_t off) {
     const int64_t halfmask = (int64_t(1) << (n - 1)) - 1;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = i >> (n - 1), k = i & halfmask;
-        const int64_t j0 = insert_zero(k, bit), j1 = j0 | (int64_t(1) << bit);
-        const cx<T> *m = mats + b * mstride + off;
-        cx<T> *p = st + (b << n);
-        const cx<T> a0 = p[j0], a1 = p[j1];
-        p[j0] = cmac(m[0], a0, cmul(m[1], a1));
-        p[j1] = cmac(m[2], a0, cmul(m[3], a1));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < total; i0 += stride * SWEEP_U) {
+        cx<T> a0[SWEEP_U], a1[SWEEP_U];
+        int64_t j0[SWEEP_U];
+#pragma unroll
+        for (int u = 0; u < SWEEP_U; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < total) {
+                const int64_t b = i >> (n - 1), k = i & halfmask;
+                j0[u] = (b << n) + insert_zero(k, bit);
+                a0[u] = st[j0[u]];
+                a1[u] = st[j0[u] + (int64_t(1) << bit)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SWEEP_U; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < total) {
+                const cx<T> *m = mats + (i >> (n - 1)) * mstride + off;
+                st[j0[u]] = cmac(m[0], a0[u], cmul(m[1], a1[u]));
+                st[j0[u] + (int64_t(1) << bit)] = cmac(m[2], a0[u], cmul(m[3], a1[u]));
+            }
+        }
     }
 }
 
@@ -758,10 +777,12 @@ __device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, co
     }
 }
 
-// One adjoint work unit: tiles t = w, w + wps, ... of one sample; per-lane
+// One adjoint work unit: tiles t = w, w + wps, ... of one sample, whose
+// state starts at st + sbase and whose lambda starts at lam + lbase; per-lane
 // float64 accumulators in LDS, reduced over the wave into partial[lslot].
 template <typename T, int R>
-__device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, int n, const int32_t *rbits,
+__device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, int64_t lbase, int n,
+                                         const int32_t *rbits,
                                          const int32_t *lbits, const int32_t *tbits, cptr<TOp> ops, int nops, int nls,
                                          cptr<cx<T>> m, int64_t w, int64_t wps, double *partial_row,
                                          const int32_t *lslot_gslot, double *acc, int lane) {
@@ -772,10 +793,10 @@ __device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, i
     const int64_t lo = lane_off(lane, lbits);
     V v[2][NR];   // [0] = psi, [1] = lambda
     for (int64_t t = w; t < tps; t += wps) {
-        int64_t base = sbase + tile_base<R>(t, tbits);   // wave-uniform
+        int64_t base = tile_base<R>(t, tbits);   // wave-uniform
         {
-            V *pp = st + base;
-            V *qp = lam + base;
+            V *pp = st + sbase + base;
+            V *qp = lam + lbase + base;
             DQ_SF(NR, {
                 v[0][i] = (pp + reg_off<R>(i, rbits))[lo];
                 v[1][i] = (qp + reg_off<R>(i, rbits))[lo];
@@ -788,8 +809,8 @@ __device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, i
         }
         asm volatile("" : "+s"(base));
         {
-            V *pp = st + base;
-            V *qp = lam + base;
+            V *pp = st + sbase + base;
+            V *qp = lam + lbase + base;
             DQ_SF(NR, {
                 (pp + reg_off<R>(i, rbits))[lo] = v[0][i];
                 (qp + reg_off<R>(i, rbits))[lo] = v[1][i];
@@ -825,7 +846,7 @@ __global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj(TileArgs a
     using V = cx<T>;
     extern __shared__ double acc[];   // [nlslots][64], one entry per lane
     const int64_t b = blockIdx.y;
-    adj_unit<T, R>((V *)a.st, (V *)a.lam, b << a.n, a.n, a.rbits, a.lbits, a.tbits, to_const(a.ops), a.nops,
+    adj_unit<T, R>((V *)a.st, (V *)a.lam, b << a.n, b << a.n, a.n, a.rbits, a.lbits, a.tbits, to_const(a.ops), a.nops,
                    a.nlslots, to_const((const V *)a.mats + b * a.mstride), blockIdx.x, a.wps,
                    a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, threadIdx.x);
 }
@@ -870,7 +891,7 @@ __global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj_multi(cx<T
     const int e = find_entry(ents, nent, u);
     const MultiEntry E = ld_entry(ents, e);
     const int64_t w = u - E.unit_begin;
-    adj_unit<T, R>(st, (V *)(ws + E.lam_off), E.st_off, E.n, E.rbits, E.lbits, E.tbits, to_const(E.ops), E.nops,
+    adj_unit<T, R>(st, (V *)(ws + E.lam_off), E.st_off, 0, E.n, E.rbits, E.lbits, E.tbits, to_const(E.ops), E.nops,
                    E.nls, to_const((const V *)(ws + E.mats_off)), w, E.wps,
                    (double *)(ws + E.part_off) + w * (int64_t)E.ngrad, E.lsg, acc, threadIdx.x);
 }

@@ -1438,6 +1438,17 @@ dq_status dq_multi_workspace_size(dq_multi m, size_t *bytes) {
     return ok();
 }
 
+dq_status dq_multi_batched(dq_multi m, int32_t *batched, int32_t *count) {
+    if (!m) return fail(DQ_ERR_INVALID_ARG, "NULL multi-plan");
+    int32_t k = 0;
+    for (size_t c = 0; c < m->plans.size(); ++c) {
+        if (batched) batched[c] = m->batched[c] ? 1 : 0;
+        k += m->batched[c] ? 1 : 0;
+    }
+    if (count) *count = k;
+    return ok();
+}
+
 dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *ws, size_t ws_bytes, void *stream) {
     if (!m || !states) return fail(DQ_ERR_INVALID_ARG, "NULL multi-plan or states");
     if (m->par_total > 0 && !params) return fail(DQ_ERR_INVALID_ARG, "params is NULL");

@@ -250,6 +250,9 @@ class Multi:
         check(lib().dq_multi_workspace_size(h, ctypes.byref(sz)), "dq_multi_workspace_size")
         self.ws_bytes = sz.value
         self.dtype = self.plans[0].dtype
+        flags = (ctypes.c_int32 * n)()
+        check(lib().dq_multi_batched(h, flags, None), "dq_multi_batched")
+        self.batched = [bool(f) for f in flags]
 
     def __del__(self):
         h = getattr(self, "_h", None)

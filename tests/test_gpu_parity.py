@@ -265,7 +265,9 @@ def test_dense_fuse_hea_family(k):
 
 
 # ------------------------------------------------------------------ uneven batches
-def _uneven(count=6, nmin=7, nmax=12, lmin=2, lmax=5):
+def _uneven(count=7, nmin=10, nmax=14, lmin=2, lmax=4):
+    # sizes chosen so that both the shared tile launches (several circuits)
+    # and the single-plan path inside the multi-plan calls are exercised
     return W.config(4, count=count, nmin=nmin, nmax=nmax, lmin=lmin, lmax=lmax)
 
 
@@ -277,6 +279,7 @@ def test_multi_plan_matches_oracle(dtype):
     plans = [dq.Plan(it.circuit, dtype) for it in mw.items]
     obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
     M = dq.Multi(plans, obs)
+    assert sum(M.batched) >= 2
     st = M.states(DEV)
     ws = M.workspace(DEV)
     params = M.pack_params([it.params for it in mw.items], DEV)
@@ -300,10 +303,11 @@ def test_multi_plan_matches_oracle(dtype):
 def test_multi_plan_graph_replay():
     """The multi-plan step captured in a HIP graph: several replays with eager
     work in between each equal the eager result."""
-    mw = _uneven(count=5, nmin=8, nmax=13)
+    mw = _uneven()
     plans = [dq.Plan(it.circuit, "c64") for it in mw.items]
     obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
     M = dq.Multi(plans, obs)
+    assert sum(M.batched) >= 2
     st, ws = M.states(DEV), M.workspace(DEV)
     params = M.pack_params([it.params for it in mw.items], DEV)
     w = torch.ones(M.nout, dtype=torch.float64, device=DEV)
@@ -333,3 +337,39 @@ def test_multi_plan_graph_replay():
         step()                       # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(E, ref_E)
+
+
+def test_uneven_full_config_multi_equals_single_plans():
+    """The full 64-circuit uneven batch (12..22 qubits): the multi-plan's
+    expectations and gradients equal those of each circuit run alone through
+    the single-plan path; circuits of up to 14 qubits also against the oracle."""
+    mw = W.config(4)
+    plans = [dq.Plan(it.circuit, "c64") for it in mw.items]
+    obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
+    M = dq.Multi(plans, obs)
+    assert all(M.batched)
+    st, ws = M.states(DEV), M.workspace(DEV)
+    params = M.pack_params([it.params for it in mw.items], DEV)
+    w = torch.ones(M.nout, dtype=torch.float64, device=DEV)
+    M.apply(st, params, ws)
+    E = M.expval(st, ws).cpu().numpy()
+    G = M.adjoint_grad(st, params, w, ws).cpu().numpy()
+    bad = []
+    for c, it in enumerate(mw.items):
+        n = it.circuit.n
+        s1 = plans[c].state(1, DEV)
+        p1 = t64(it.params)
+        dq.apply_circuit(plans[c], s1, p1, None, from_zero=True)
+        e1 = dq.expval(plans[c], obs[c], s1).cpu().numpy()[0, 0]
+        g1, _ = dq.adjoint_grad(plans[c], obs[c], s1, p1, None, t64(np.ones((1, 1))))
+        g1 = g1.cpu().numpy()
+        gm = G[M.param_off[c]:M.param_off[c] + it.circuit.n_params]
+        ok_e = abs(E[M.out_off[c]] - e1) <= 1e-9 * max(1.0, abs(e1))
+        ok_g = np.all(np.isfinite(gm)) and np.linalg.norm(gm - g1) <= 1e-9 * max(1e-12, np.linalg.norm(g1))
+        if not (ok_e and ok_g):
+            bad.append((c, n, len(it.circuit.gates), float(E[M.out_off[c]]), float(e1),
+                        float(np.linalg.norm(gm - g1)), bool(np.all(np.isfinite(gm)))))
+        if n <= 14:
+            want = oracle.expvals(n, oracle.state(it.circuit, it.params), it.observables)[0]
+            normwise([e1], [want], 1e-5, 1e-6, "circuit %d expval vs oracle" % c)
+    assert not bad, "multi vs single plan differ (c, n, gates, E_multi, E_single, |dg|, finite): %s" % bad[:8]

@@ -38,7 +38,7 @@ METRIC = "HBM GB/s per gate sweep; fwd+adjoint-grad circuits/sec vs plain path"
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "runtime.cpp", "dq_internal.h"):
+    for f in ("kernels.hip", "tiles.hip", "tile_dev.h", "jit.cpp", "runtime.cpp", "dq_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2512_18995_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -230,8 +230,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg5", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--tile-bits", type=int, default=0)
+    ap.add_argument("--adj-tile-bits", type=int, default=0)
     ap.add_argument("--dense-fuse", type=int, default=0, choices=[0, 4, 5],
                     help="forward sweep as fused dense k-qubit blocks on the matrix cores")
+    ap.add_argument("--interpret", action="store_true",
+                    help="run the tile passes interpreted (op lists read at run time) instead of compiled at plan time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-layers", type=int, default=2)
@@ -266,7 +269,8 @@ def main():
     wl = W.config(cid)
     c = wl.circuit
     B = wl.batch
-    plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits, dense_fuse=args.dense_fuse)
+    plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits, dense_fuse=args.dense_fuse, jit=not args.interpret,
+                   adj_tile_bits=args.adj_tile_bits)
     obs = dq.Observable(c.n, wl.observables)
     params = torch.as_tensor(wl.params, dtype=torch.float64, device=dev)
     data = None if wl.data is None else torch.as_tensor(wl.data, dtype=torch.float64, device=dev)
@@ -291,9 +295,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
+    # the first step sets the plan up on the device (uploads; compiles the
+    # distinct tile passes unless interpreted): timed apart, untimed warm-up
+    first_step_s = None
+    for i in range(args.warmup):
+        t_first = time.perf_counter()
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        if i == 0:
+            first_step_s = time.perf_counter() - t_first
     plan.profile_enable(True)
     plan.profile_read(reset=True)
     torch.cuda.synchronize()                                    # barrier is trivial at one rank
@@ -400,7 +410,10 @@ def main():
         "kernels": kernels,
         "plan": {"fwd_tile_passes": st["fwd_tile_passes"], "fwd_dense_blocks": st["fwd_dense_blocks"],
                  "adj_steps": st["adj_steps"],
-                 "folded_gates": st["folded_gates"], "tile_bits": st["tile_bits"]},
+                 "folded_gates": st["folded_gates"], "tile_bits": st["tile_bits"],
+                 "adj_tile_bits": st["adj_tile_bits"],
+                 "passes": "interpreted" if args.interpret else "compiled",
+                 "compiled_kernels": len(plan.jit_sources()), "first_step_s": first_step_s},
         "checks": checks,
         "source_hash": kernel_source_hash(),
     }

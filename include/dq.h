@@ -114,12 +114,20 @@ typedef struct {
     int32_t fusion;       /* 1 (default): register-tile passes that apply many gates per
                              state sweep; 0: the plain path, one kernel launch per gate */
     int32_t tile_bits;    /* register-resident wires per tile: 0 = auto (5 for complex64,
-                             4 for complex128); 1..6 (complex128: 1..5) */
+                             4 for complex128; with jit 6 and 5); 1..6 (complex128: 1..5) */
     int32_t fold_init;    /* 1 (default): fold the leading one-qubit gates of every wire into
                              the initial product-state write when applying from |0..0> */
     int32_t dense_fuse;   /* 0 (default): register tiles; 4 or 5: the forward sweep groups gates
                              into dense blocks on k wires (product of the gate matrices, formed
                              on the device in double) applied on the matrix cores (MFMA) */
+    int32_t jit;          /* 0 (default): register-tile passes read their operation list at run
+                             time; 1: each distinct pass is compiled (hipRTC, at the plan's first
+                             use on a device; code objects cached in DQ_JIT_CACHE, default
+                             $HOME/.cache/dq_jit) into straight-line code with every operand
+                             position a compile-time constant */
+    int32_t adj_tile_bits; /* register-resident wires per tile of the adjoint sweep, which holds
+                             two states: 0 = auto (min(tile bits, 4) for complex64, 3 for
+                             complex128; with jit 5 and 4); 1..5 (complex128: 1..4) */
 } dq_options;
 
 typedef struct dq_plan_s *dq_plan;
@@ -136,7 +144,14 @@ typedef struct {
     int64_t adj_steps;        /* sweeps of the (state, adjoint) pair in dq_adjoint_grad */
     int64_t folded_gates;     /* gates folded into the initial product state */
     int64_t grad_gates;       /* gate occurrences that carry a gradient */
-    int32_t tile_bits;
+    int32_t tile_bits;        /* register bits of the forward tiles */
+    int32_t adj_tile_bits;    /* register bits of the adjoint tiles */
+    /* register-tile operations of the forward program (index 0) and the
+     * adjoint program (index 1) by kind: 0 dense 2x2, 1 diagonal 2x2, 2 CNOT,
+     * 3 CZ, 4 two-qubit diagonal, 5 swap, 6 real 2x2, 7 RX form; [.][0][k]
+     * counts operations whose target is a lane bit (cross-lane exchange),
+     * [.][1][k] those on register bits */
+    int64_t tile_ops[2][2][8];
 } dq_plan_stats;
 
 /* Build a plan for an n-qubit circuit (host only; no device work).
@@ -148,6 +163,18 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
                          int64_t nparams, int64_t ndata, dq_dtype dtype, const dq_options *opt);
 void dq_plan_destroy(dq_plan plan);
 dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out);
+/* Text description of the forward and adjoint programs, one line per step:
+ * "<fwd|adj> <index> tile R=.. lbits=.. rbits=.. ops=kind:q0:q1:gen:slot:lslot;..."
+ * for register-tile passes (q = tile-local bit: < 6 lane, else register
+ * q - 6), "<fwd|adj> <index> sweep kind=.. k=.. bits=.. slot=.. gen=.. gslot=.."
+ * for whole-state sweeps.  Writes at most cap bytes including the
+ * terminating NUL; *needed (nullable) receives the full size.  Host only. */
+dq_status dq_plan_describe(dq_plan plan, char *buf, size_t cap, size_t *needed);
+/* Plans created with jit = 1: *count (nullable) receives the number of
+ * distinct compiled pass kernels; for 0 <= index < count, the kernel's source
+ * (it includes "tile_dev.h") is written as by dq_plan_describe.  index < 0
+ * only sets *count.  Host only. */
+dq_status dq_plan_jit_source(dq_plan plan, int32_t index, char *buf, size_t cap, size_t *needed, int32_t *count);
 
 /* Observables: nobs Pauli sums over the terms [obs_offsets[o], obs_offsets[o+1]).
  * Host only; masks must not touch wires >= nqubits. */

@@ -24,7 +24,8 @@ EXPORTS = ["dq_plan_create", "dq_plan_destroy", "dq_plan_get_stats", "dq_obs_cre
            "dq_workspace_size", "dq_state_init", "dq_apply_circuit", "dq_expval", "dq_adjoint_grad",
            "dq_last_error", "dq_version", "dq_profile_enable", "dq_profile_read",
            "dq_multi_create", "dq_multi_destroy", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
-           "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched"]
+           "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe",
+           "dq_plan_jit_source"]
 PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other", "dense"]
 
 
@@ -38,13 +39,15 @@ class DqPauliTerm(ctypes.Structure):
 
 
 class DqOptions(ctypes.Structure):
-    _fields_ = [("fusion", c_int32), ("tile_bits", c_int32), ("fold_init", c_int32), ("dense_fuse", c_int32)]
+    _fields_ = [("fusion", c_int32), ("tile_bits", c_int32), ("fold_init", c_int32), ("dense_fuse", c_int32),
+                ("jit", c_int32), ("adj_tile_bits", c_int32)]
 
 
 class DqPlanStats(ctypes.Structure):  # noqa: E302
     _fields_ = [("nqubits", c_int32), ("dtype", c_int32), ("ngates", c_int64), ("fwd_steps", c_int64),
                 ("fwd_tile_passes", c_int64), ("fwd_dense_blocks", c_int64), ("adj_steps", c_int64),
-                ("folded_gates", c_int64), ("grad_gates", c_int64), ("tile_bits", c_int32)]
+                ("folded_gates", c_int64), ("grad_gates", c_int64), ("tile_bits", c_int32), ("adj_tile_bits", c_int32),
+                ("tile_ops", ((c_int64 * 8) * 2) * 2)]
 
 
 class DqProfile(ctypes.Structure):
@@ -91,6 +94,8 @@ def lib():
         L.dq_multi_layout.argtypes = [vp, i64p, i64p, i64p, i64p, i64p, i64p]
         L.dq_multi_workspace_size.argtypes = [vp, POINTER(c_size_t)]
         L.dq_multi_batched.argtypes = [vp, POINTER(c_int32), POINTER(c_int32)]
+        L.dq_plan_describe.argtypes = [vp, c_char_p, c_size_t, POINTER(c_size_t)]
+        L.dq_plan_jit_source.argtypes = [vp, c_int32, c_char_p, c_size_t, POINTER(c_size_t), POINTER(c_int32)]
         L.dq_multi_apply.argtypes = [vp, vp, vp, vp, c_size_t, vp]
         L.dq_multi_expval.argtypes = [vp, vp, vp, vp, c_size_t, vp]
         L.dq_multi_adjoint_grad.argtypes = [vp, vp, vp, vp, vp, vp, c_size_t, vp]
@@ -99,7 +104,7 @@ def lib():
         for f in ("dq_plan_create", "dq_plan_get_stats", "dq_obs_create", "dq_workspace_size", "dq_state_init",
                   "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read",
                   "dq_multi_create", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
-                  "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched"):
+                  "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe", "dq_plan_jit_source"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib

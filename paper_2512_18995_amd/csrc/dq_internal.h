@@ -4,6 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
+#include "tile_dev.h"
+
 namespace dq {
 
 // ---------------------------------------------------------------- gates
@@ -13,11 +18,6 @@ enum : int32_t {
     OP_UNITARY
 };
 enum : int32_t { SRC_NONE = 0, SRC_PARAM = 1, SRC_DATA = 2 };
-
-// Generator of a differentiable gate, as seen by the adjoint sweep:
-//   GEN_X/Y/Z (one wire), GEN_ZZ (two wires) for exp(-i t G / 2)  -> dE/dt = Im<l|G|p>
-//   GEN_P11 (|11><11| on two wires) for CP(t) = exp(i t P11)         -> dE/dt = -2 Im<l|P11|p>
-enum : int32_t { GEN_NONE = 0, GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_ZZ = 4, GEN_P11 = 5 };
 
 struct DGate {                 // device copy of one gate
     int32_t op, nq;
@@ -51,32 +51,6 @@ struct DBlock {
     int32_t bb[5];
     int64_t off;               // complex offset inside one sample's matrix block
 };
-
-// ---------------------------------------------------------------- tile passes
-// Tile-local bit q: 0..5 = lane bits, 6..6+R-1 = register bits.  Lane bits 0..2
-// are physical bits 0..2 in every pass (each group of 8 lanes reads 8
-// consecutive amplitudes); lane bits 3..5 are physical lbits[0..2] and
-// register bit q is physical rbits[q-6], chosen per pass.
-enum : int32_t {
-    TK_1Q = 0,      // dense 2x2 on q0
-    TK_1QDIAG = 1,  // diagonal 2x2 on q0 (entries m00, m11 of the slot)
-    TK_CNOT = 2,    // control q0, target q1
-    TK_CZ = 3,      // q0, q1
-    TK_2QDIAG = 4,  // diagonal 4x4 on (q0 = msb, q1) (entries 0, 5, 10, 15 of the slot)
-    TK_SWAP = 5,    // exchange q0 and q1
-    TK_1QREAL = 6,  // real 2x2 on q0 (real parts of the slot)
-    TK_1QRX = 7     // [[c, i s], [i s, c]] on q0 (c = Re m00, s = Im m01)
-};
-
-struct TOp {
-    int32_t kind;
-    int32_t q0, q1;
-    int32_t gen;       // adjoint: generator whose expectation is accumulated before un-applying
-    int32_t slot;      // complex offset of the matrix inside one sample's block
-    int32_t lslot;     // adjoint: accumulator index inside the pass, -1 none
-};
-
-enum : int32_t { MAX_TILE_R = 6, MAX_LSLOTS = 64 };
 
 // One circuit's tile pass inside a multi-circuit launch.  Offsets: st_off in
 // amplitudes from the packed state base; lam_off, mats_off, part_off in bytes
@@ -115,23 +89,6 @@ struct DGroup {
 // on `stream`; they return the hipGetLastError() of the launch.
 namespace dq {
 
-struct TileArgs {
-    void *st;                  // state [B][2^n]
-    void *lam;                 // adjoint state (adjoint passes only)
-    int32_t n, R;
-    int32_t rbits[MAX_TILE_R]; // physical bits of the register bits
-    int32_t lbits[3];          // physical bits of lane bits 3..5
-    int32_t tbits[MAX_TILE_R + 3];  // lbits and rbits together, ascending
-    int64_t batch;
-    const TOp *ops;
-    int32_t nops, nlslots;
-    const void *mats;          // per-sample matrix blocks
-    int64_t mstride;           // complex elements between samples' blocks (0 = shared)
-    double *partial;           // adjoint: [B][wps][ngrad]
-    const int32_t *lslot_gslot;// adjoint: global gradient index of each local slot
-    int32_t wps, ngrad;
-};
-
 hipError_t launch_prepare(int dbl, const DGate *gates, const void *fixed, const DSlot *slots,
                           int32_t nslots, const double *params, int64_t pstride, const double *data,
                           int64_t dstride, void *mats, int64_t block, int64_t bm, hipStream_t s);
@@ -154,6 +111,30 @@ hipError_t launch_gatek(int dbl, void *st, int32_t n, int64_t batch, int32_t k, 
 // (complex64) or n >= k + 4 (complex128)
 hipError_t launch_dense(int dbl, void *st, int32_t n, int64_t batch, int32_t k, const int32_t *bits, const void *mats,
                         int64_t mstride, int64_t off, hipStream_t s);
+// per-precision entry points of the interpreted tile passes (tiles.hip)
+hipError_t tile_fwd_f32(const TileArgs &a, hipStream_t s);
+hipError_t tile_fwd_f64(const TileArgs &a, hipStream_t s);
+hipError_t tile_adj_f32(const TileArgs &a, hipStream_t s);
+hipError_t tile_adj_f64(const TileArgs &a, hipStream_t s);
+int tile_adj_capacity_f32(int R);
+int tile_adj_capacity_f64(int R);
+hipError_t tile_fwd_multi_f32(int R, void *st, const void *ws, const MultiEntry *e, int32_t n, int64_t units,
+                              hipStream_t s);
+hipError_t tile_fwd_multi_f64(int R, void *st, const void *ws, const MultiEntry *e, int32_t n, int64_t units,
+                              hipStream_t s);
+hipError_t tile_adj_multi_f32(int R, void *st, void *ws, const MultiEntry *e, int32_t n, int64_t units, size_t lds,
+                              hipStream_t s);
+hipError_t tile_adj_multi_f64(int R, void *st, void *ws, const MultiEntry *e, int32_t n, int64_t units, size_t lds,
+                              hipStream_t s);
+// passes compiled at plan time (jit.cpp): jit_key names the kernel of a
+// source body (a hash that also covers tile_dev.h and the compiler options);
+// jit_load returns, for the current device, the kernels of the given names
+// and full sources, compiling what neither the process nor the disk cache
+// holds; jit_launch runs one on a tile argument block.
+std::string jit_key(const std::string &body);
+bool jit_load(const std::vector<std::string> &names, const std::vector<std::string> &srcs,
+              std::vector<hipFunction_t> &out, std::string &err);
+hipError_t jit_launch(hipFunction_t f, const std::string &name, const TileArgs &a, bool adj, hipStream_t s);
 hipError_t launch_tile_fwd(int dbl, const TileArgs &a, hipStream_t s);
 hipError_t launch_tile_adj(int dbl, const TileArgs &a, hipStream_t s);
 // resident single-wave workgroups of the adjoint tile kernel on the current device

@@ -27,95 +27,6 @@
 namespace dq {
 namespace {
 
-// Compile-time loop: every index is a constant expression, so register
-// arrays indexed by it stay in VGPRs.
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
-}
-#define DQ_SF(N, ...) static_for<0, (N)>([&](auto ic_) { constexpr int i = decltype(ic_)::value; __VA_ARGS__; })
-// The same, with a scheduling barrier after every 8 elements: loops that
-// issue cross-lane shuffles would otherwise hoist all of them and hold every
-// result in registers at once.
-#define DQ_SF8(N, ...)                                                       \
-    static_for<0, (N)>([&](auto ic_) {                                      \
-        constexpr int i = decltype(ic_)::value;                             \
-        __VA_ARGS__;                                                        \
-        if constexpr ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);      \
-    })
-
-// Read-only tables (op lists, gate matrices) are read through the constant
-// address space so that wave-uniform reads become scalar loads.
-template <typename T> using cptr = __attribute__((address_space(4))) const T *;
-template <typename T> __device__ __forceinline__ cptr<T> to_const(const T *p) { return (cptr<T>)(uintptr_t)p; }
-template <typename V> __device__ __forceinline__ V ldc(cptr<V> p, int k) { return V{p[k].x, p[k].y}; }
-// MultiEntry read field by field from the constant address space (scalar loads)
-__device__ __forceinline__ MultiEntry ld_entry(cptr<MultiEntry> ents, int e) {
-    MultiEntry E;
-    E.st_off = ents[e].st_off;
-    E.lam_off = ents[e].lam_off;
-    E.mats_off = ents[e].mats_off;
-    E.part_off = ents[e].part_off;
-    E.unit_begin = ents[e].unit_begin;
-    E.ops = ents[e].ops;
-    E.lsg = ents[e].lsg;
-    E.n = ents[e].n;
-    E.nops = ents[e].nops;
-    E.nls = ents[e].nls;
-    E.wps = ents[e].wps;
-    E.ngrad = ents[e].ngrad;
-    for (int k = 0; k < MAX_TILE_R; ++k) E.rbits[k] = ents[e].rbits[k];
-    for (int k = 0; k < 3; ++k) E.lbits[k] = ents[e].lbits[k];
-    for (int k = 0; k < MAX_TILE_R + 3; ++k) E.tbits[k] = ents[e].tbits[k];
-    return E;
-}
-
-__device__ __forceinline__ TOp ld_op(cptr<TOp> ops, int k) {
-    const cptr<int32_t> w = (cptr<int32_t>)(ops + k);
-    TOp o;
-    o.kind = w[0];
-    o.q0 = w[1];
-    o.q1 = w[2];
-    o.gen = w[3];
-    o.slot = w[4];
-    o.lslot = w[5];
-    return o;
-}
-
-// Amplitudes are a plain aligned pair (not HIP's union-based float2/double2,
-// which keeps register arrays of it from being promoted to VGPRs).
-template <typename T> struct alignas(2 * sizeof(T)) cpx {
-    T x, y;
-};
-template <typename T> using cx = cpx<T>;
-using C64 = cpx<float>;
-using C128 = cpx<double>;
-
-__device__ __forceinline__ float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
-    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-// a * b + c
-template <typename V> __device__ __forceinline__ V cmac(V a, V b, V c) {
-    return V{fm(a.x, b.x, fm(-a.y, b.y, c.x)), fm(a.x, b.y, fm(a.y, b.x, c.y))};
-}
-template <typename V> __device__ __forceinline__ V cneg(V a) { return V{-a.x, -a.y}; }
-// component-wise select (a struct-valued ?: becomes a pointer select plus a
-// copy through memory, which keeps register arrays out of VGPRs)
-template <typename V> __device__ __forceinline__ V csel(bool c, V a, V b) { return V{c ? a.x : b.x, c ? a.y : b.y}; }
-
-template <typename V> __device__ __forceinline__ V shfl_xor_c(V a, int mask) {
-    return V{__shfl_xor(a.x, mask), __shfl_xor(a.y, mask)};
-}
-
-__device__ __forceinline__ int64_t insert_zero(int64_t x, int b) {
-    return ((x >> b) << (b + 1)) | (x & ((int64_t(1) << b) - 1));
-}
 
 inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 16) {
     int64_t g = (work + block - 1) / block;
@@ -427,473 +338,6 @@ __global__ __launch_bounds__(256) void k_gatek(cx<T> *st, int n, int64_t total, 
             p[of] = o[x];
         }
     }
-}
-
-// ============================================================ register tiles
-// Tile-local index u = (register index i) << 6 | lane.  Bit q of u: lane bit
-// for q < 6, register bit q-6 otherwise.
-__device__ __forceinline__ bool tbit(int i, int lane, int q) {
-    // the lane half does not depend on i (hoisted out of the register loop);
-    // the register half is wave-uniform (scalar ALU)
-    return q < 6 ? ((lane >> q) & 1) : ((i >> (q - 6)) & 1);
-}
-
-template <int K> struct Pair {   // the i-th index pair (i0, i1) differing in register bit K
-    static constexpr int lo(int i) { return ((i >> K) << (K + 1)) | (i & ((1 << K) - 1)); }
-    static constexpr int hi(int i) { return lo(i) | (1 << K); }
-};
-
-// Every op below updates NS state arrays of NR register amplitudes (NS = 1
-// in the forward sweep, 2 = (psi, lambda) in the adjoint sweep), so that one
-// dispatch serves both states and their arithmetic interleaves.
-#define DQ_NS(...) static_for<0, NS>([&](auto sc_) { constexpr int s_ = decltype(sc_)::value; __VA_ARGS__; })
-
-template <typename V, int NS, int NR, int K>
-__device__ __forceinline__ void reg_1q(V (&v)[NS][NR], V m00, V m01, V m10, V m11) {
-    DQ_SF(NR / 2, {
-        constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
-        DQ_NS({
-            const V a0 = v[s_][i0], a1 = v[s_][i1];
-            v[s_][i0] = cmac(m00, a0, cmul(m01, a1));
-            v[s_][i1] = cmac(m10, a0, cmul(m11, a1));
-        });
-    });
-}
-
-// real 2x2 (RY and products of RY, H, X, Z): 8 FMA per pair instead of 16
-template <typename V, int NS, int NR, int K, typename T>
-__device__ __forceinline__ void reg_1q_real(V (&v)[NS][NR], T m00, T m01, T m10, T m11) {
-    DQ_SF(NR / 2, {
-        constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
-        DQ_NS({
-            const V a0 = v[s_][i0], a1 = v[s_][i1];
-            v[s_][i0] = V{fm(m00, a0.x, m01 * a1.x), fm(m00, a0.y, m01 * a1.y)};
-            v[s_][i1] = V{fm(m10, a0.x, m11 * a1.x), fm(m10, a0.y, m11 * a1.y)};
-        });
-    });
-}
-
-// [[c, i s], [i s, c]] (RX and its dagger): 8 FMA per pair
-template <typename V, int NS, int NR, int K, typename T>
-__device__ __forceinline__ void reg_1q_rx(V (&v)[NS][NR], T c, T s) {
-    DQ_SF(NR / 2, {
-        constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
-        DQ_NS({
-            const V a0 = v[s_][i0], a1 = v[s_][i1];
-            v[s_][i0] = V{fm(c, a0.x, -s * a1.y), fm(c, a0.y, s * a1.x)};
-            v[s_][i1] = V{fm(c, a1.x, -s * a0.y), fm(c, a1.y, s * a0.x)};
-        });
-    });
-}
-
-template <typename V, int NS, int NR, int K>
-__device__ __forceinline__ void reg_1q_diag(V (&v)[NS][NR], V d0, V d1) {
-    DQ_SF(NR, { DQ_NS({ v[s_][i] = cmul(((i >> K) & 1) ? d1 : d0, v[s_][i]); }); });
-}
-
-template <typename V, int NS, int NR, int K>
-__device__ __forceinline__ void reg_cnot(V (&v)[NS][NR], int cq, int lane) {
-    DQ_SF(NR / 2, {
-        constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
-        const bool c = tbit(i0, lane, cq);
-        DQ_NS({
-            const V a0 = v[s_][i0], a1 = v[s_][i1];
-            v[s_][i0] = csel(c, a1, a0);
-            v[s_][i1] = csel(c, a0, a1);
-        });
-    });
-}
-
-// swap of two register bits K1 < K2
-template <typename V, int NS, int NR, int K1, int K2>
-__device__ __forceinline__ void reg_swap(V (&v)[NS][NR]) {
-    DQ_SF(NR, {
-        if constexpr (((i >> K1) & 1) && !((i >> K2) & 1)) {
-            constexpr int j = i ^ (1 << K1) ^ (1 << K2);
-            DQ_NS({
-                const V t = v[s_][i];
-                v[s_][i] = v[s_][j];
-                v[s_][j] = t;
-            });
-        }
-    });
-}
-
-// swap of lane bit l with register bit K
-template <typename V, int NS, int NR, int K>
-__device__ __forceinline__ void lane_reg_swap(V (&v)[NS][NR], int l, int lane) {
-    const bool hl = (lane >> l) & 1;
-    DQ_SF8(NR / 2, {
-        constexpr int i0 = Pair<K>::lo(i), i1 = Pair<K>::hi(i);
-        DQ_NS({
-            const V o0 = shfl_xor_c(v[s_][i1], 1 << l), o1 = shfl_xor_c(v[s_][i0], 1 << l);
-            v[s_][i0] = csel(hl, o0, v[s_][i0]);
-            v[s_][i1] = csel(hl, v[s_][i1], o1);
-        });
-    });
-}
-
-template <typename T, typename V, int NR, int K>
-__device__ __forceinline__ T reg_xy_sum(const V (&v)[NR], const V (&l)[NR], bool isY) {
-    T s = 0;
-    DQ_SF(NR, {
-        V o = v[i ^ (1 << K)];
-        if (isY) o = csel(((i >> K) & 1) != 0, V{-o.y, o.x}, V{o.y, -o.x});   // (Yv)_1 = i v_0, (Yv)_0 = -i v_1
-        s += l[i].x * o.y - l[i].y * o.x;
-    });
-    return s;
-}
-
-#define DQ_REG_DISPATCH(k, NR, CALL)                                          \
-    switch (k) {                                                              \
-    case 0: if constexpr (NR > 1) { constexpr int K_ = 0; CALL; } break;      \
-    case 1: if constexpr (NR > 2) { constexpr int K_ = 1; CALL; } break;      \
-    case 2: if constexpr (NR > 4) { constexpr int K_ = 2; CALL; } break;      \
-    case 3: if constexpr (NR > 8) { constexpr int K_ = 3; CALL; } break;      \
-    case 4: if constexpr (NR > 16) { constexpr int K_ = 4; CALL; } break;     \
-    case 5: if constexpr (NR > 32) { constexpr int K_ = 5; CALL; } break;     \
-    default: break;                                                           \
-    }
-
-template <typename V, int NS, int NR, int K1>
-__device__ __forceinline__ void reg_swap_k2(V (&v)[NS][NR], int k2) {
-    switch (k2) {
-    case 1: if constexpr (NR > 2 && K1 < 1) reg_swap<V, NS, NR, K1, 1>(v); break;
-    case 2: if constexpr (NR > 4 && K1 < 2) reg_swap<V, NS, NR, K1, 2>(v); break;
-    case 3: if constexpr (NR > 8 && K1 < 3) reg_swap<V, NS, NR, K1, 3>(v); break;
-    case 4: if constexpr (NR > 16 && K1 < 4) reg_swap<V, NS, NR, K1, 4>(v); break;
-    case 5: if constexpr (NR > 32 && K1 < 5) reg_swap<V, NS, NR, K1, 5>(v); break;
-    default: break;
-    }
-}
-
-template <typename T, int NS, int NR>
-__device__ __forceinline__ void apply_op(cx<T> (&v)[NS][NR], const TOp &op, cptr<cx<T>> m, int lane) {
-    using V = cx<T>;
-    switch (op.kind) {
-    case TK_1Q: {
-        const V m00 = ldc(m, op.slot), m01 = ldc(m, op.slot + 1), m10 = ldc(m, op.slot + 2), m11 = ldc(m, op.slot + 3);
-        if (op.q0 < 6) {
-            const bool hi = (lane >> op.q0) & 1;
-            const V cs = csel(hi, m11, m00), co = csel(hi, m10, m01);
-            DQ_SF8(NR, { DQ_NS({ v[s_][i] = cmac(cs, v[s_][i], cmul(co, shfl_xor_c(v[s_][i], 1 << op.q0))); }); });
-        } else {
-            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q<V, NS, NR, K_>(v, m00, m01, m10, m11)));
-        }
-        break;
-    }
-    case TK_1QREAL: {
-        const T m00 = m[op.slot].x, m01 = m[op.slot + 1].x, m10 = m[op.slot + 2].x, m11 = m[op.slot + 3].x;
-        if (op.q0 < 6) {
-            const bool hi = (lane >> op.q0) & 1;
-            const T cs = hi ? m11 : m00, co = hi ? m10 : m01;
-            DQ_SF8(NR, {
-                DQ_NS({
-                    const V o = shfl_xor_c(v[s_][i], 1 << op.q0);
-                    v[s_][i] = V{fm(cs, v[s_][i].x, co * o.x), fm(cs, v[s_][i].y, co * o.y)};
-                });
-            });
-        } else {
-            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q_real<V, NS, NR, K_, T>(v, m00, m01, m10, m11)));
-        }
-        break;
-    }
-    case TK_1QRX: {
-        const T c = m[op.slot].x, sn = m[op.slot + 1].y;   // m01 = i s
-        if (op.q0 < 6) {
-            DQ_SF8(NR, {
-                DQ_NS({
-                    const V o = shfl_xor_c(v[s_][i], 1 << op.q0);
-                    v[s_][i] = V{fm(c, v[s_][i].x, -sn * o.y), fm(c, v[s_][i].y, sn * o.x)};
-                });
-            });
-        } else {
-            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q_rx<V, NS, NR, K_, T>(v, c, sn)));
-        }
-        break;
-    }
-    case TK_1QDIAG: {
-        const V d0 = ldc(m, op.slot), d1 = ldc(m, op.slot + 3);
-        if (op.q0 < 6) {
-            const V d = csel(((lane >> op.q0) & 1) != 0, d1, d0);   // one factor per lane
-            DQ_SF(NR, { DQ_NS({ v[s_][i] = cmul(d, v[s_][i]); }); });
-        } else {
-            DQ_REG_DISPATCH(op.q0 - 6, NR, (reg_1q_diag<V, NS, NR, K_>(v, d0, d1)));
-        }
-        break;
-    }
-    case TK_CNOT: {
-        if (op.q1 < 6) {
-            DQ_SF8(NR, {
-                const bool c = tbit(i, lane, op.q0);
-                DQ_NS({
-                    const V o = shfl_xor_c(v[s_][i], 1 << op.q1);
-                    v[s_][i] = csel(c, o, v[s_][i]);
-                });
-            });
-        } else {
-            DQ_REG_DISPATCH(op.q1 - 6, NR, (reg_cnot<V, NS, NR, K_>(v, op.q0, lane)));
-        }
-        break;
-    }
-    case TK_CZ: {
-        DQ_SF(NR, {
-            const bool c = tbit(i, lane, op.q0) && tbit(i, lane, op.q1);
-            DQ_NS({ v[s_][i] = csel(c, cneg(v[s_][i]), v[s_][i]); });
-        });
-        break;
-    }
-    case TK_2QDIAG: {
-        const V d0 = ldc(m, op.slot), d1 = ldc(m, op.slot + 5), d2 = ldc(m, op.slot + 10), d3 = ldc(m, op.slot + 15);
-        DQ_SF(NR, {
-            const bool a = tbit(i, lane, op.q0), b = tbit(i, lane, op.q1);
-            const V d = csel(a, csel(b, d3, d2), csel(b, d1, d0));
-            DQ_NS({ v[s_][i] = cmul(d, v[s_][i]); });
-        });
-        break;
-    }
-    case TK_SWAP: {
-        const int a = op.q0 < op.q1 ? op.q0 : op.q1, b = op.q0 < op.q1 ? op.q1 : op.q0;
-        if (b < 6) {
-            const int mask = (1 << a) | (1 << b);
-            const bool differ = ((lane >> a) ^ (lane >> b)) & 1;
-            DQ_SF8(NR, {
-                DQ_NS({
-                    const V o = shfl_xor_c(v[s_][i], mask);
-                    v[s_][i] = csel(differ, o, v[s_][i]);
-                });
-            });
-        } else if (a < 6) {
-            DQ_REG_DISPATCH(b - 6, NR, (lane_reg_swap<V, NS, NR, K_>(v, a, lane)));
-        } else {
-            DQ_REG_DISPATCH(a - 6, NR, (reg_swap_k2<V, NS, NR, K_>(v, b - 6)));
-        }
-        break;
-    }
-    default: break;
-    }
-}
-
-// sum over this lane's register amplitudes of Im(conj(l) * (G v))
-template <typename T, int NR>
-__device__ __forceinline__ T gen_local(const cx<T> (&v)[NR], const cx<T> (&l)[NR], const TOp &op, int lane) {
-    using V = cx<T>;
-    T s = 0;
-    switch (op.gen) {
-    case GEN_Z:
-        DQ_SF(NR, {
-            const T t = l[i].x * v[i].y - l[i].y * v[i].x;
-            s += tbit(i, lane, op.q0) ? -t : t;
-        });
-        break;
-    case GEN_ZZ:
-        DQ_SF(NR, {
-            const T t = l[i].x * v[i].y - l[i].y * v[i].x;
-            s += (tbit(i, lane, op.q0) != tbit(i, lane, op.q1)) ? -t : t;
-        });
-        break;
-    case GEN_P11:
-        DQ_SF(NR, {
-            const T t = l[i].x * v[i].y - l[i].y * v[i].x;
-            s += (tbit(i, lane, op.q0) && tbit(i, lane, op.q1)) ? t : T(0);
-        });
-        break;
-    case GEN_X:
-    case GEN_Y: {
-        const bool isY = op.gen == GEN_Y;
-        if (op.q0 < 6) {
-            DQ_SF8(NR, {
-                V o = shfl_xor_c(v[i], 1 << op.q0);
-                if (isY) o = csel(((lane >> op.q0) & 1) != 0, V{-o.y, o.x}, V{o.y, -o.x});
-                s += l[i].x * o.y - l[i].y * o.x;
-            });
-        } else {
-            DQ_REG_DISPATCH(op.q0 - 6, NR, (s = reg_xy_sum<T, V, NR, K_>(v, l, isY)));
-        }
-        break;
-    }
-    default: break;
-    }
-    return s;
-}
-
-// first amplitude of tile t: the tile index fills every physical bit that is
-// not a tile bit (bits 0..2 and the 3 + R chosen bits are zero)
-template <int R>
-__device__ __forceinline__ int64_t tile_base(int64_t t, const int32_t *tb) {
-    int64_t base = t << 3;
-#pragma unroll
-    for (int k = 0; k < R + 3; ++k) base = insert_zero(base, tb[k]);
-    return base;
-}
-
-// this lane's offset inside a tile: lane bits 0..2 -> physical 0..2,
-// lane bits 3..5 -> lbits[0..2]
-__device__ __forceinline__ int64_t lane_off(int lane, const int32_t *lb) {
-    int64_t o = lane & 7;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if ((lane >> (3 + k)) & 1) o += int64_t(1) << lb[k];
-    return o;
-}
-
-template <int R>
-__device__ __forceinline__ int64_t reg_off(int i, const int32_t *rb) {
-    int64_t o = 0;
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-        if ((i >> k) & 1) o += int64_t(1) << rb[k];
-    return o;
-}
-
-// occupancy target (waves per SIMD) of the register tiles: two for the
-// largest tiles, more for small ones
-template <typename T, int R> constexpr int tile_waves() { return (1 << R) * sizeof(T) >= 256 ? 1 : ((1 << R) * sizeof(T) >= 128 ? 2 : 3); }
-// the adjoint holds two states per lane: two waves per SIMD up to 16
-// complex64 (8 complex128) amplitudes per state
-template <typename T, int R> constexpr int adj_waves() { return (1 << R) * sizeof(T) >= 128 ? 1 : ((1 << R) * sizeof(T) >= 64 ? 2 : 4); }
-
-// One forward tile: load 2^R amplitudes per lane, run the op list, store.
-template <typename T, int R>
-__device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, const int32_t *rbits, cptr<TOp> ops,
-                                         int nops, cptr<cx<T>> m, int lane) {
-    using V = cx<T>;
-    constexpr int NR = 1 << R;
-    V v[1][NR];
-    {
-        V *tp = st + base;
-        DQ_SF(NR, { v[0][i] = (tp + reg_off<R>(i, rbits))[lo]; });
-    }
-    for (int k = 0; k < nops; ++k) {
-        const TOp op = ld_op(ops, k);
-        apply_op<T, 1, NR>(v, op, m, lane);
-    }
-    // recompute the addresses for the stores rather than keeping the loads'
-    // 2^R per-lane pointers alive across the op loop
-    asm volatile("" : "+s"(base));
-    {
-        V *tp = st + base;
-        DQ_SF(NR, { (tp + reg_off<R>(i, rbits))[lo] = v[0][i]; });
-    }
-}
-
-// One adjoint work unit: tiles t = w, w + wps, ... of one sample, whose
-// state starts at st + sbase and whose lambda starts at lam + lbase; per-lane
-// float64 accumulators in LDS, reduced over the wave into partial[lslot].
-template <typename T, int R>
-__device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, int64_t lbase, int n,
-                                         const int32_t *rbits,
-                                         const int32_t *lbits, const int32_t *tbits, cptr<TOp> ops, int nops, int nls,
-                                         cptr<cx<T>> m, int64_t w, int64_t wps, double *partial_row,
-                                         const int32_t *lslot_gslot, double *acc, int lane) {
-    using V = cx<T>;
-    constexpr int NR = 1 << R;
-    const int64_t tps = int64_t(1) << (n - 6 - R);
-    for (int s = 0; s < nls; ++s) acc[s * 64 + lane] = 0.0;
-    const int64_t lo = lane_off(lane, lbits);
-    V v[2][NR];   // [0] = psi, [1] = lambda
-    for (int64_t t = w; t < tps; t += wps) {
-        int64_t base = tile_base<R>(t, tbits);   // wave-uniform
-        {
-            V *pp = st + sbase + base;
-            V *qp = lam + lbase + base;
-            DQ_SF(NR, {
-                v[0][i] = (pp + reg_off<R>(i, rbits))[lo];
-                v[1][i] = (qp + reg_off<R>(i, rbits))[lo];
-            });
-        }
-        for (int k = 0; k < nops; ++k) {
-            const TOp op = ld_op(ops, k);
-            if (op.lslot >= 0) acc[op.lslot * 64 + lane] += (double)gen_local<T, NR>(v[0], v[1], op, lane);
-            apply_op<T, 2, NR>(v, op, m, lane);
-        }
-        asm volatile("" : "+s"(base));
-        {
-            V *pp = st + sbase + base;
-            V *qp = lam + lbase + base;
-            DQ_SF(NR, {
-                (pp + reg_off<R>(i, rbits))[lo] = v[0][i];
-                (qp + reg_off<R>(i, rbits))[lo] = v[1][i];
-            });
-        }
-    }
-    for (int s = 0; s < nls; ++s) {
-        double x = acc[s * 64 + lane];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        if (lane == 0) partial_row[lslot_gslot[s]] = x;
-    }
-}
-
-template <typename T, int R>
-__global__ __launch_bounds__(64, (tile_waves<T, R>())) void k_tile_fwd(TileArgs a) {
-    using V = cx<T>;
-    const int lane = threadIdx.x;
-    const int tshift = a.n - 6 - R;
-    const int64_t total = a.batch << tshift;
-    const int64_t tmask = (int64_t(1) << tshift) - 1;
-    const int64_t lo = lane_off(lane, a.lbits);
-    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        const int64_t b = tile >> tshift;
-        const int64_t base = (b << a.n) + tile_base<R>(tile & tmask, a.tbits);   // wave-uniform
-        fwd_tile<T, R>((V *)a.st, base, lo, a.rbits, to_const(a.ops), a.nops,
-                       to_const((const V *)a.mats + b * a.mstride), lane);
-    }
-}
-
-template <typename T, int R>
-__global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj(TileArgs a) {
-    using V = cx<T>;
-    extern __shared__ double acc[];   // [nlslots][64], one entry per lane
-    const int64_t b = blockIdx.y;
-    adj_unit<T, R>((V *)a.st, (V *)a.lam, b << a.n, b << a.n, a.n, a.rbits, a.lbits, a.tbits, to_const(a.ops), a.nops,
-                   a.nlslots, to_const((const V *)a.mats + b * a.mstride), blockIdx.x, a.wps,
-                   a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, threadIdx.x);
-}
-
-// ---------------------------------------------------------------- uneven batches
-// One launch runs the tile pass of the same depth for every circuit of a
-// multi-plan: work unit u belongs to the entry e with unit_begin[e] <= u <
-// unit_begin[e + 1]; pointers are base + per-entry offsets.
-__device__ __forceinline__ int find_entry(cptr<MultiEntry> ents, int nent, int64_t u) {
-    int lo = 0, hi = nent - 1;
-    while (lo < hi) {                       // last entry with unit_begin <= u
-        const int mid = (lo + hi + 1) >> 1;
-        if (ents[mid].unit_begin <= u) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <typename T, int R>
-__global__ __launch_bounds__(64, (tile_waves<T, R>())) void k_tile_fwd_multi(cx<T> *st, const char *ws,
-                                                                             const MultiEntry *ents_, int nent,
-                                                                             int64_t units) {
-    using V = cx<T>;
-    const cptr<MultiEntry> ents = to_const(ents_);
-    const int lane = threadIdx.x;
-    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int e = find_entry(ents, nent, u);
-        const MultiEntry E = ld_entry(ents, e);
-        const int64_t base = E.st_off + tile_base<R>(u - E.unit_begin, E.tbits);
-        fwd_tile<T, R>(st, base, lane_off(lane, E.lbits), E.rbits, to_const(E.ops), E.nops,
-                       to_const((const V *)(ws + E.mats_off)), lane);
-    }
-}
-
-template <typename T, int R>
-__global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj_multi(cx<T> *st, char *ws,
-                                                                            const MultiEntry *ents_, int nent) {
-    using V = cx<T>;
-    extern __shared__ double acc[];
-    const cptr<MultiEntry> ents = to_const(ents_);
-    const int64_t u = blockIdx.x;
-    const int e = find_entry(ents, nent, u);
-    const MultiEntry E = ld_entry(ents, e);
-    const int64_t w = u - E.unit_begin;
-    adj_unit<T, R>(st, (V *)(ws + E.lam_off), E.st_off, 0, E.n, E.rbits, E.lbits, E.tbits, to_const(E.ops), E.nops,
-                   E.nls, to_const((const V *)(ws + E.mats_off)), w, E.wps,
-                   (double *)(ws + E.part_off) + w * (int64_t)E.ngrad, E.lsg, acc, threadIdx.x);
 }
 
 // ============================================================ matrix-core dense blocks
@@ -1355,31 +799,6 @@ hipError_t launch_gatek(int dbl, void *st, int32_t n, int64_t batch, int32_t k, 
     DQ_LAUNCH_RET;
 }
 
-// Resident single-wave workgroups of a tile kernel on the current device
-// (occupancy x compute units), cached per device and instantiation.
-template <typename K>
-static int resident_waves(K kernel, size_t lds, int key) {
-    static int cache[64][32];
-    static bool init = false;
-    if (!init) {
-        for (auto &r : cache)
-            for (int &c : r) c = 0;
-        init = true;
-    }
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev >= 64) dev = 0;
-    int &c = cache[dev][key & 31];
-    if (c == 0) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, lds) != hipSuccess || per_cu < 1)
-            per_cu = 2;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 256;
-        c = per_cu * cus;
-    }
-    return c;
-}
-
 hipError_t launch_dense(int dbl, void *st, int32_t n, int64_t batch, int32_t k, const int32_t *bits, const void *mats,
                         int64_t mstride, int64_t off, hipStream_t s) {
     DenseBits db;
@@ -1401,129 +820,21 @@ hipError_t launch_dense(int dbl, void *st, int32_t n, int64_t batch, int32_t k, 
     DQ_LAUNCH_RET;
 }
 
-static unsigned tile_grid(int64_t tiles, int resident) {
-    // one resident wave per slot; each wave walks a strided subset of the tiles
-    const int64_t cap = resident > 0 ? resident : 4096;
-    return (unsigned)(tiles < cap ? (tiles < 1 ? 1 : tiles) : cap);
-}
-
-template <typename T, int R>
-static void tile_fwd_r(const TileArgs &a, hipStream_t s) {
-    const int key = (sizeof(T) == 8 ? 16 : 0) + R;
-    const unsigned g = tile_grid(a.batch << (a.n - 6 - R), resident_waves(k_tile_fwd<T, R>, 0, key));
-    hipLaunchKernelGGL((k_tile_fwd<T, R>), dim3(g), dim3(64), 0, s, a);
-}
-
-template <typename T>
-static void tile_fwd_t(const TileArgs &a, hipStream_t s) {
-    switch (a.R) {
-    case 1: tile_fwd_r<T, 1>(a, s); break;
-    case 2: tile_fwd_r<T, 2>(a, s); break;
-    case 3: tile_fwd_r<T, 3>(a, s); break;
-    case 4: tile_fwd_r<T, 4>(a, s); break;
-    case 5: tile_fwd_r<T, 5>(a, s); break;
-    default:
-        if constexpr (sizeof(T) == 4) tile_fwd_r<T, 6>(a, s);
-        break;
-    }
-}
-
 hipError_t launch_tile_fwd(int dbl, const TileArgs &a, hipStream_t s) {
-    if (dbl) {
-        if (a.R > 5) return hipErrorInvalidValue;
-        tile_fwd_t<double>(a, s);
-    } else {
-        tile_fwd_t<float>(a, s);
-    }
-    DQ_LAUNCH_RET;
-}
-
-template <typename T>
-static void tile_adj_t(const TileArgs &a, hipStream_t s) {
-    dim3 g((unsigned)a.wps, (unsigned)a.batch);
-    const size_t lds = sizeof(double) * 64 * (a.nlslots > 0 ? a.nlslots : 1);
-    switch (a.R) {
-    case 1: hipLaunchKernelGGL((k_tile_adj<T, 1>), g, dim3(64), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tile_adj<T, 2>), g, dim3(64), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_tile_adj<T, 3>), g, dim3(64), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_tile_adj<T, 4>), g, dim3(64), lds, s, a); break;
-    default:
-        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_tile_adj<T, 5>), g, dim3(64), lds, s, a);
-        break;
-    }
-}
-
-int tile_adj_capacity(int dbl, int R) {
-    const size_t lds = sizeof(double) * 64 * 32;     // the most accumulator slots a pass may use
-    const int key = 8 + (dbl ? 16 : 0) + R;
-    if (dbl) {
-        switch (R) {
-        case 1: return resident_waves(k_tile_adj<double, 1>, lds, key);
-        case 2: return resident_waves(k_tile_adj<double, 2>, lds, key);
-        case 3: return resident_waves(k_tile_adj<double, 3>, lds, key);
-        default: return resident_waves(k_tile_adj<double, 4>, lds, key);
-        }
-    }
-    switch (R) {
-    case 1: return resident_waves(k_tile_adj<float, 1>, lds, key);
-    case 2: return resident_waves(k_tile_adj<float, 2>, lds, key);
-    case 3: return resident_waves(k_tile_adj<float, 3>, lds, key);
-    case 4: return resident_waves(k_tile_adj<float, 4>, lds, key);
-    default: return resident_waves(k_tile_adj<float, 5>, lds, key);
-    }
+    return dbl ? tile_fwd_f64(a, s) : tile_fwd_f32(a, s);
 }
 
 hipError_t launch_tile_adj(int dbl, const TileArgs &a, hipStream_t s) {
     if (a.nlslots > MAX_LSLOTS) return hipErrorInvalidValue;
-    if (dbl) {
-        if (a.R > 4) return hipErrorInvalidValue;
-        tile_adj_t<double>(a, s);
-    } else {
-        if (a.R > 5) return hipErrorInvalidValue;
-        tile_adj_t<float>(a, s);
-    }
-    DQ_LAUNCH_RET;
+    return dbl ? tile_adj_f64(a, s) : tile_adj_f32(a, s);
 }
 
-template <typename T>
-static hipError_t fwd_multi_t(int R, void *st, const void *ws, const MultiEntry *e, int32_t n, int64_t units,
-                              hipStream_t s) {
-    const unsigned g = (unsigned)(units < 16384 ? units : 16384);
-    switch (R) {
-    case 3: hipLaunchKernelGGL((k_tile_fwd_multi<T, 3>), dim3(g), dim3(64), 0, s, (cx<T> *)st, (const char *)ws, e, n, units); break;
-    case 4: hipLaunchKernelGGL((k_tile_fwd_multi<T, 4>), dim3(g), dim3(64), 0, s, (cx<T> *)st, (const char *)ws, e, n, units); break;
-    case 5:
-        if constexpr (sizeof(T) == 4) {
-            hipLaunchKernelGGL((k_tile_fwd_multi<T, 5>), dim3(g), dim3(64), 0, s, (cx<T> *)st, (const char *)ws, e, n, units);
-            break;
-        }
-        return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
+int tile_adj_capacity(int dbl, int R) { return dbl ? tile_adj_capacity_f64(R) : tile_adj_capacity_f32(R); }
 
 hipError_t launch_tile_fwd_multi(int dbl, int R, void *st, const void *ws, const MultiEntry *ents, int32_t nent,
                                  int64_t units, hipStream_t s) {
     if (units <= 0) return hipSuccess;
-    return dbl ? fwd_multi_t<double>(R, st, ws, ents, nent, units, s) : fwd_multi_t<float>(R, st, ws, ents, nent, units, s);
-}
-
-template <typename T>
-static hipError_t adj_multi_t(int R, void *st, void *ws, const MultiEntry *e, int32_t n, int64_t units, size_t lds,
-                              hipStream_t s) {
-    const unsigned g = (unsigned)units;
-    switch (R) {
-    case 3: hipLaunchKernelGGL((k_tile_adj_multi<T, 3>), dim3(g), dim3(64), lds, s, (cx<T> *)st, (char *)ws, e, n); break;
-    case 4:
-        if constexpr (sizeof(T) == 4) {
-            hipLaunchKernelGGL((k_tile_adj_multi<T, 4>), dim3(g), dim3(64), lds, s, (cx<T> *)st, (char *)ws, e, n);
-            break;
-        }
-        return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return dbl ? tile_fwd_multi_f64(R, st, ws, ents, nent, units, s) : tile_fwd_multi_f32(R, st, ws, ents, nent, units, s);
 }
 
 hipError_t launch_tile_adj_multi(int dbl, int R, void *st, void *ws, const MultiEntry *ents, int32_t nent,
@@ -1531,8 +842,8 @@ hipError_t launch_tile_adj_multi(int dbl, int R, void *st, void *ws, const Multi
     if (units <= 0) return hipSuccess;
     if (max_nls > MAX_LSLOTS || units > 0x7fffffff) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * 64 * (max_nls > 0 ? max_nls : 1);
-    return dbl ? adj_multi_t<double>(R, st, ws, ents, nent, units, lds, s)
-               : adj_multi_t<float>(R, st, ws, ents, nent, units, lds, s);
+    return dbl ? tile_adj_multi_f64(R, st, ws, ents, nent, units, lds, s)
+               : tile_adj_multi_f32(R, st, ws, ents, nent, units, lds, s);
 }
 
 hipError_t launch_grad_gate(int dbl, const void *psi, const void *lam, int32_t n, int64_t batch, int32_t gen,

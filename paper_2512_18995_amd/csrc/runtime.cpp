@@ -113,12 +113,17 @@ struct Step {
 
 struct Program {
     std::vector<Step> steps;
+    // compiled passes (option jit): per step, the index of its kernel in the
+    // plan's kernel list (-1: interpreted) and the pass's first matrix slot
+    std::vector<int> jk;
+    std::vector<int64_t> js0;
     int64_t slot_lo = 0, slot_hi = 0;  // slot index range used (for prepare)
     int64_t blk_lo = 0, blk_hi = 0;    // fused dense block range used
     int64_t tile_passes = 0, dense_steps = 0;
 };
 
 struct DevData {
+    std::vector<hipFunction_t> jfn;   // compiled passes, in the plan's kernel-list order
     void *blob = nullptr;
     DGate *gates = nullptr;
     double2 *fixed = nullptr;
@@ -150,6 +155,7 @@ struct dq_plan_s {
     std::vector<int32_t> lsg;
     Program fwd_full, fwd_fold, adj;
     bool has_fold = false;
+    std::vector<std::string> jnames, jsrcs;   // compiled passes: kernel names and sources
     std::vector<int64_t> fold_off;      // per physical bit: slot offset of the folded column, -1 none
     int64_t folded_gates = 0;
     int R_fwd = 0, R_adj = 0;
@@ -217,7 +223,17 @@ struct Planner {
     dq_plan_s &p;
     bool adjoint;
     int R;
-    explicit Planner(dq_plan_s &pl, bool adj, int r) : p(pl), adjoint(adj), R(r) {}
+    // Physical bits 3 and 4 in every tile of a large state: each group of 16
+    // lanes then reads 128 contiguous bytes and each register pair 256.
+    // Tiles whose bits are all high physical bits scatter every wave's
+    // accesses over the whole state in 64-byte pieces, which halves the
+    // bandwidth the memory system sustains once the state no longer fits the
+    // last-level cache.
+    uint64_t pinned = 0;
+    explicit Planner(dq_plan_s &pl, bool adj, int r) : p(pl), adjoint(adj), R(r) {
+        const int64_t state_bytes = (int64_t)(p.dbl ? 16 : 8) << p.n;
+        if (R >= 2 && p.n >= R + 8 && state_bytes >= (int64_t(128) << 20)) pinned = (1ull << 3) | (1ull << 4);
+    }
 
     void gbits(int g, int *q, int &nq) const {
         nq = p.gates[g].nq;
@@ -397,10 +413,10 @@ struct Planner {
             }
             // candidate register sets: unseeded, and seeded by each of the
             // first few gates that need non-lane bits
-            uint64_t bestS = 0;
+            uint64_t bestS = pinned;
             std::vector<int> best;
             {
-                uint64_t S = 0;
+                uint64_t S = pinned;
                 best = select(rem, S, -1);
                 bestS = S;
             }
@@ -411,7 +427,7 @@ struct Planner {
                 for (int i = 0; i < G.nq; ++i) hi |= G.bits[i] >= 3;
                 if (!hi || !tile_ok(rem[r])) continue;
                 ++tried;
-                uint64_t S = 0;
+                uint64_t S = pinned;
                 std::vector<int> sel = select(rem, S, (int)r);
                 if (sel.size() > best.size()) {
                     best = sel;
@@ -441,6 +457,15 @@ struct Planner {
             for (int b = 3; b < p.n; ++b)
                 if (bestS >> b & 1) freeb.push_back(b);
             std::stable_sort(freeb.begin(), freeb.end(), [&](int x, int y) { return moves[x] < moves[y]; });
+            if (pinned) {   // lane bit 3 = physical bit 3, physical bit 4 a register bit
+                std::vector<int> rest;
+                for (int b : freeb)
+                    if (b != 3 && b != 4) rest.push_back(b);
+                freeb.assign({3});
+                freeb.insert(freeb.end(), rest.begin(), rest.begin() + 2);
+                freeb.push_back(4);
+                freeb.insert(freeb.end(), rest.begin() + 2, rest.end());
+            }
             Step st;
             st.kind = ST_TILE;
             st.R = R;
@@ -553,9 +578,11 @@ struct Planner {
 };
 
 int default_R(const dq_plan_s &p) {
-    // defaults keep two resident waves per SIMD (complex64: 32 amplitudes per
-    // lane, complex128: 16)
-    int R = p.opt.tile_bits > 0 ? p.opt.tile_bits : (p.dbl ? 4 : 5);
+    // defaults keep two resident waves per SIMD: interpreted passes hold 32
+    // complex64 (16 complex128) amplitudes per lane; compiled passes, which
+    // need no registers for dispatch, hold twice that
+    const int base = p.opt.jit ? (p.dbl ? 5 : 6) : (p.dbl ? 4 : 5);
+    int R = p.opt.tile_bits > 0 ? p.opt.tile_bits : base;
     if (p.dbl && R > 5) R = 5;
     if (R > p.n - 6) R = p.n - 6;
     return R < 0 ? 0 : R;
@@ -565,7 +592,11 @@ dq_status build_plan(dq_plan_s &p) {
     const int G = (int)p.gates.size();
     const bool fused = p.opt.fusion != 0;
     p.R_fwd = fused ? default_R(p) : 0;
-    p.R_adj = std::min(p.R_fwd, p.dbl ? 3 : 4);   // two states per tile in the adjoint
+    // two states per tile in the adjoint: fewer register bits by default
+    const int abase = p.opt.jit ? (p.dbl ? 4 : 5) : (p.dbl ? 3 : 4);
+    int ra = p.opt.adj_tile_bits > 0 ? p.opt.adj_tile_bits : std::min(p.R_fwd, abase);
+    if (ra > p.n - 6) ra = p.n - 6;
+    p.R_adj = fused && ra > 0 ? ra : 0;
     // gradient slots: every differentiable gate occurrence, in gate order
     std::vector<int> gslot(G, -1);
     p.ngrad = 0;
@@ -661,6 +692,82 @@ size_t put(std::vector<char> &blob, const std::vector<T> &v) {
     return off;
 }
 
+// ---------------------------------------------------------------- compiled passes
+// Source of the kernel that runs one tile pass as straight-line code: every
+// operation becomes a call with compile-time operand positions (tile-local
+// bits; matrix slots relative to the pass's first matrix, whose address the
+// launch passes in).  Passes with equal operation lists share one kernel.
+bool has_matrix(int kind) {
+    return kind == TK_1Q || kind == TK_1QDIAG || kind == TK_2QDIAG || kind == TK_1QREAL || kind == TK_1QRX;
+}
+
+std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) {
+    s0 = -1;
+    for (int64_t i = 0; i < S.nops; ++i) {
+        const TOp &o = p.ops[(size_t)(S.op0 + i)];
+        if (has_matrix(o.kind) && (s0 < 0 || o.slot < s0)) s0 = o.slot;
+    }
+    if (s0 < 0) s0 = 0;
+    const char *T = p.dbl ? "double" : "float";
+    const int R = S.R, NR = 1 << R, NS = adj ? 2 : 1;
+    // occupancy target, as for the interpreted passes (waves per SIMD)
+    const int rb = NR * (p.dbl ? 8 : 4);
+    const int W = adj ? (rb >= 128 ? 1 : (rb >= 64 ? 2 : 4)) : (rb >= 256 ? 1 : (rb >= 128 ? 2 : 3));
+    char line[256];
+    std::string b;
+    snprintf(line, sizeof line, "__launch_bounds__(64, %d) void @NAME@(dq::TileArgs a) {\n", W);
+    b += line;
+    if (adj) {
+        snprintf(line, sizeof line,
+                 "    extern __shared__ double acc[];\n"
+                 "    dq::jit_adj<%s, %d>(a, acc, [&](auto &v, auto m, int lane, double *ac) {\n", T, R);
+    } else {
+        snprintf(line, sizeof line, "    dq::jit_fwd<%s, %d>(a, [&](auto &v, auto m, int lane) {\n", T, R);
+    }
+    b += line;
+    for (int64_t i = 0; i < S.nops; ++i) {
+        const TOp &o = p.ops[(size_t)(S.op0 + i)];
+        if (adj && o.lslot >= 0) {
+            snprintf(line, sizeof line, "        ac[%d * 64 + lane] += (double)dq::gen_s<%s, %d, %d, %d, %d>(v[0], v[1], lane);\n",
+                     o.lslot, T, NR, o.gen, o.q0, o.q1);
+            b += line;
+        }
+        snprintf(line, sizeof line, "        dq::op_s<%s, %d, %d, %d, %d, %d, %lld>(v, m, lane);\n", T, NS, NR, o.kind, o.q0,
+                 o.q1, has_matrix(o.kind) ? (long long)(o.slot - s0) : 0ll);
+        b += line;
+    }
+    b += "    });\n}\n";
+    return b;
+}
+
+void jit_generate(dq_plan_s &p) {
+    std::map<std::string, int> index;
+    auto gen = [&](Program &prog, bool adj) {
+        prog.jk.assign(prog.steps.size(), -1);
+        prog.js0.assign(prog.steps.size(), 0);
+        for (size_t k = 0; k < prog.steps.size(); ++k) {
+            const Step &S = prog.steps[k];
+            if (S.kind != ST_TILE) continue;
+            int64_t s0 = 0;
+            const std::string body = pass_body(p, S, adj, s0);
+            auto it = index.find(body);
+            if (it == index.end()) {
+                const std::string name = jit_key(body);
+                std::string src = "#include \"tile_dev.h\"\nextern \"C\" __global__ " + body;
+                src.replace(src.find("@NAME@"), 6, name);
+                it = index.emplace(body, (int)p.jnames.size()).first;
+                p.jnames.push_back(name);
+                p.jsrcs.push_back(src);
+            }
+            prog.jk[k] = it->second;
+            prog.js0[k] = s0;
+        }
+    };
+    gen(p.fwd_full, false);
+    if (p.has_fold) gen(p.fwd_fold, false);
+    gen(p.adj, true);
+}
+
 dq_status ensure_device(dq_plan_s &p, DevData **out) {
     int dev = 0;
     DQ_HIP(hipGetDevice(&dev));
@@ -700,6 +807,13 @@ dq_status ensure_device(dq_plan_s &p, DevData **out) {
     dd.doff = (int64_t *)(b + o_do);
     dd.dg = (int32_t *)(b + o_dg);
     dd.df = (double *)(b + o_df);
+    if (!p.jnames.empty()) {
+        std::string err;
+        if (!jit_load(p.jnames, p.jsrcs, dd.jfn, err)) {
+            (void)hipFree(dd.blob);
+            return fail(DQ_ERR_INTERNAL, "%s", err.c_str());
+        }
+    }
     *out = &(p.dev[dev] = dd);
     return DQ_OK;
 }
@@ -809,7 +923,13 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
             a.lslot_gslot = d.lsg + S.ls0;
             a.wps = wps;
             a.ngrad = p.ngrad;
-            e = lam ? launch_tile_adj(p.dbl, a, s) : launch_tile_fwd(p.dbl, a, s);
+            const size_t si = (size_t)(&S - prog.steps.data());
+            if (!prog.jk.empty() && prog.jk[si] >= 0 && (size_t)prog.jk[si] < d.jfn.size()) {
+                a.mats = (const char *)mats + prog.js0[si] * (p.dbl ? 16 : 8);
+                e = jit_launch(d.jfn[prog.jk[si]], p.jnames[prog.jk[si]], a, lam != nullptr, s);
+            } else {
+                e = lam ? launch_tile_adj(p.dbl, a, s) : launch_tile_fwd(p.dbl, a, s);
+            }
             break;
         }
         case ST_GRAD:
@@ -870,8 +990,11 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     if (ngates > (1 << 24)) return fail(DQ_ERR_OUT_OF_RANGE, "too many gates (%lld)", (long long)ngates);
     if (nparams < 0 || ndata < 0) return fail(DQ_ERR_INVALID_ARG, "negative nparams / ndata");
     if (dtype != DQ_C64 && dtype != DQ_C128) return fail(DQ_ERR_UNSUPPORTED, "dtype %d", (int)dtype);
-    dq_options o{1, 0, 1, 0};
+    dq_options o{1, 0, 1, 0, 0, 0};
     if (opt) o = *opt;
+    if (o.adj_tile_bits < 0 || o.adj_tile_bits > (dtype == DQ_C128 ? 4 : 5))
+        return fail(DQ_ERR_INVALID_ARG, "adj_tile_bits %d outside 0..%d", o.adj_tile_bits, dtype == DQ_C128 ? 4 : 5);
+    if (o.jit != 0 && o.jit != 1) return fail(DQ_ERR_INVALID_ARG, "jit must be 0 or 1 (got %d)", o.jit);
     if (o.tile_bits < 0 || o.tile_bits > 6) return fail(DQ_ERR_INVALID_ARG, "tile_bits %d outside 0..6", o.tile_bits);
     if (o.dense_fuse != 0 && o.dense_fuse != 4 && o.dense_fuse != 5)
         return fail(DQ_ERR_INVALID_ARG, "dense_fuse must be 0, 4 or 5 (got %d)", o.dense_fuse);
@@ -944,6 +1067,7 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
         delete p;
         return st;
     }
+    if (o.jit) jit_generate(*p);
     *out = p;
     return ok();
 }
@@ -976,7 +1100,79 @@ dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) {
     s.folded_gates = plan->folded_gates;
     s.grad_gates = plan->ngrad;
     s.tile_bits = plan->R_fwd;
+    s.adj_tile_bits = plan->R_adj;
+    for (int which = 0; which < 2; ++which) {
+        const Program &prog = which ? plan->adj : f;
+        for (const Step &S : prog.steps) {
+            if (S.kind != ST_TILE) continue;
+            for (int64_t k = 0; k < S.nops; ++k) {
+                const TOp &o = plan->ops[(size_t)(S.op0 + k)];
+                if (o.kind < 0 || o.kind > 7) continue;
+                // the bit the operation exchanges amplitudes over (none for diagonals)
+                int tq = o.q0;
+                if (o.kind == TK_CNOT) tq = o.q1;
+                if (o.kind == TK_SWAP) tq = std::min(o.q0, o.q1);
+                const bool diag = o.kind == TK_1QDIAG || o.kind == TK_CZ || o.kind == TK_2QDIAG;
+                s.tile_ops[which][(!diag && tq < 6) ? 0 : 1][o.kind] += 1;
+            }
+        }
+    }
     *out = s;
+    return ok();
+}
+
+dq_status dq_plan_describe(dq_plan plan, char *buf, size_t cap, size_t *needed) {
+    if (!plan) return fail(DQ_ERR_INVALID_ARG, "NULL plan");
+    std::string t;
+    char line[256];
+    const Program &f = plan->has_fold ? plan->fwd_fold : plan->fwd_full;
+    for (int which = 0; which < 2; ++which) {
+        const Program &prog = which ? plan->adj : f;
+        for (size_t k = 0; k < prog.steps.size(); ++k) {
+            const Step &S = prog.steps[k];
+            if (S.kind == ST_TILE) {
+                snprintf(line, sizeof line, "%s %zu tile R=%d lbits=%d,%d,%d rbits=", which ? "adj" : "fwd", k, S.R,
+                         S.lbits[0], S.lbits[1], S.lbits[2]);
+                t += line;
+                for (int i = 0; i < S.R; ++i) t += std::to_string(S.rbits[i]) + (i + 1 < S.R ? "," : "");
+                t += " ops=";
+                for (int64_t i = 0; i < S.nops; ++i) {
+                    const TOp &o = plan->ops[(size_t)(S.op0 + i)];
+                    snprintf(line, sizeof line, "%s%d:%d:%d:%d:%d:%d", i ? ";" : "", o.kind, o.q0, o.q1, o.gen, o.slot,
+                             o.lslot);
+                    t += line;
+                }
+                t += "\n";
+            } else {
+                snprintf(line, sizeof line, "%s %zu sweep kind=%d k=%d bits=%d,%d,%d,%d,%d slot=%lld gen=%d gslot=%d\n",
+                         which ? "adj" : "fwd", k, S.kind, S.k, S.bits[0], S.bits[1], S.bits[2], S.bits[3], S.bits[4],
+                         (long long)S.slot, S.gen, S.gslot);
+                t += line;
+            }
+        }
+    }
+    if (needed) *needed = t.size() + 1;
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, t.size());
+        memcpy(buf, t.data(), n);
+        buf[n] = 0;
+    }
+    return ok();
+}
+
+dq_status dq_plan_jit_source(dq_plan plan, int32_t index, char *buf, size_t cap, size_t *needed, int32_t *count) {
+    if (!plan) return fail(DQ_ERR_INVALID_ARG, "NULL plan");
+    if (count) *count = (int32_t)plan->jsrcs.size();
+    if (index < 0) return ok();
+    if ((size_t)index >= plan->jsrcs.size())
+        return fail(DQ_ERR_OUT_OF_RANGE, "pass kernel %d of %zu", index, plan->jsrcs.size());
+    const std::string &t = plan->jsrcs[(size_t)index];
+    if (needed) *needed = t.size() + 1;
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, t.size());
+        memcpy(buf, t.data(), n);
+        buf[n] = 0;
+    }
     return ok();
 }
 

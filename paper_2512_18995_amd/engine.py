@@ -30,14 +30,16 @@ class Plan:
     its first use on a device)."""
 
     def __init__(self, circuit, dtype: str = "c64", fusion: bool = True, tile_bits: int = 0,
-                 fold_init: bool = True, dense_fuse: int = 0):
+                 fold_init: bool = True, dense_fuse: int = 0, jit: bool = False, adj_tile_bits: int = 0):
         self.n = int(circuit.n)
         self.dtype = dtype
         self.nparams = int(circuit.n_params)
         self.ndata = int(circuit.n_data)
         self.gates = list(circuit.gates)
         arr, keep = _lib.gate_array(self.gates)
-        opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, int(dense_fuse))
+        opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, int(dense_fuse),
+                             1 if jit else 0, int(adj_tile_bits))
+        self.jit = bool(jit)
         h = ctypes.c_void_p()
         check(lib().dq_plan_create(ctypes.byref(h), self.n, arr, len(self.gates), self.nparams, self.ndata,
                                    _lib.C64 if dtype == "c64" else _lib.C128, ctypes.byref(opt)), "dq_plan_create")
@@ -60,7 +62,34 @@ class Plan:
     def stats(self) -> dict:
         s = _lib.DqPlanStats()
         check(lib().dq_plan_get_stats(self._h, ctypes.byref(s)), "dq_plan_get_stats")
-        return {k: getattr(s, k) for k, _ in _lib.DqPlanStats._fields_}
+        out = {k: getattr(s, k) for k, _ in _lib.DqPlanStats._fields_ if k != "tile_ops"}
+        kinds = ["1q", "1q_diag", "cnot", "cz", "2q_diag", "swap", "1q_real", "1q_rx"]
+        for w, prog in enumerate(("fwd", "adj")):
+            for where, name in enumerate(("lane", "reg")):
+                out["%s_ops_%s" % (prog, name)] = {kinds[k]: int(s.tile_ops[w][where][k]) for k in range(8)
+                                                   if s.tile_ops[w][where][k]}
+        return out
+
+    def describe(self) -> str:
+        """One line per kernel step of the forward and adjoint programs."""
+        need = ctypes.c_size_t()
+        check(lib().dq_plan_describe(self._h, None, 0, ctypes.byref(need)), "dq_plan_describe")
+        buf = ctypes.create_string_buffer(need.value)
+        check(lib().dq_plan_describe(self._h, buf, need.value, None), "dq_plan_describe")
+        return buf.value.decode()
+
+    def jit_sources(self) -> list:
+        """Sources of the plan's compiled pass kernels (jit plans; else empty)."""
+        cnt = ctypes.c_int32()
+        check(lib().dq_plan_jit_source(self._h, -1, None, 0, None, ctypes.byref(cnt)), "dq_plan_jit_source")
+        out = []
+        for i in range(cnt.value):
+            need = ctypes.c_size_t()
+            check(lib().dq_plan_jit_source(self._h, i, None, 0, ctypes.byref(need), None), "dq_plan_jit_source")
+            buf = ctypes.create_string_buffer(need.value)
+            check(lib().dq_plan_jit_source(self._h, i, buf, need.value, None, None), "dq_plan_jit_source")
+            out.append(buf.value.decode())
+        return out
 
     def profile_enable(self, on: bool = True):
         """Bracket every kernel launch of this plan with hipEvents."""

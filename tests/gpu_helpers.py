@@ -18,9 +18,9 @@ def rand_state(rng, n):
     return x / np.linalg.norm(x)
 
 
-def gpu_forward(circuit, params, data, batch, dtype, fusion=True, init=None, tile_bits=0, fold=True):
+def gpu_forward(circuit, params, data, batch, dtype, fusion=True, init=None, tile_bits=0, fold=True, jit=False):
     """Final states [B, 2^n] (numpy complex128) of the HIP path."""
-    plan = dq.Plan(circuit, dtype, fusion=fusion, tile_bits=tile_bits, fold_init=fold)
+    plan = dq.Plan(circuit, dtype, fusion=fusion, tile_bits=tile_bits, fold_init=fold, jit=jit)
     st = plan.state(batch, DEV)
     if init is not None:
         dq.state_init(plan, st, torch.as_tensor(np.asarray(init), dtype=CT[dtype], device=DEV))

@@ -143,3 +143,59 @@ def test_calls_validate_before_device_work(L):
     assert lib.dq_adjoint_grad(h, o, fake, 1, fake, 0, None, 0, fake, fake, None, 0, fake, 1 << 20, None) == 1
     lib.dq_obs_destroy(o)
     lib.dq_plan_destroy(h)
+
+
+def test_jit_option_validation_and_sources(L):
+    """jit must be 0 or 1; a jit plan lists one kernel per distinct tile pass,
+    and passes that repeat (equal operation lists) share a kernel."""
+    from workloads import config
+    st, h = _create(L, 8, [G("ry", (q,), "param", q) for q in range(8)], 8, 0, opt=L.DqOptions(1, 0, 1, 0, 2))
+    assert st == 1 and "jit" in L.lib().dq_last_error().decode()
+    import paper_2512_18995_amd as dq
+    w = config(5, n=16, layers=8)
+    plain = dq.Plan(w.circuit, "c64")
+    assert plain.jit_sources() == []
+    p = dq.Plan(w.circuit, "c64", jit=True)
+    srcs = p.jit_sources()
+    steps = [l for l in p.describe().splitlines() if " tile " in l]
+    assert 0 < len(srcs) < len(steps)
+    assert all('#include "tile_dev.h"' in s and "dq::op_s<" in s for s in srcs)
+    assert any("dq::gen_s<" in s for s in srcs)   # adjoint passes accumulate gradient terms
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/lib/libhiprtc.so"), reason="hipRTC not installed")
+def test_jit_source_compiles_for_gfx950(L):
+    """The generated pass kernels compile with hipRTC against tile_dev.h for
+    gfx950 (host-side check; no device needed), and the packed FP32
+    instructions stay disabled."""
+    import subprocess
+    import tempfile
+    import paper_2512_18995_amd as dq
+    from workloads import config
+    rtc = ctypes.CDLL("/opt/rocm/lib/libhiprtc.so")
+    hdr = open(os.path.join(os.path.dirname(L.LIB_PATH), "csrc", "tile_dev.h")).read().encode()
+    w = config(5, n=12, layers=2)
+    srcs = dq.Plan(w.circuit, "c64", jit=True).jit_sources()
+    opts = [b"-O3", b"-std=c++17", b"-Xclang", b"-target-feature", b"-Xclang", b"-packed-fp32-ops",
+            b"--offload-arch=gfx950"]
+    for src in (srcs[0], srcs[-1]):   # a forward and an adjoint pass
+        prog = ctypes.c_void_p()
+        hs, hn = (ctypes.c_char_p * 1)(hdr), (ctypes.c_char_p * 1)(b"tile_dev.h")
+        assert rtc.hiprtcCreateProgram(ctypes.byref(prog), src.encode(), b"pass.hip", 1, hs, hn) == 0
+        r = rtc.hiprtcCompileProgram(prog, len(opts), (ctypes.c_char_p * len(opts))(*opts))
+        n = ctypes.c_size_t()
+        rtc.hiprtcGetProgramLogSize(prog, ctypes.byref(n))
+        log = ctypes.create_string_buffer(n.value + 1)
+        rtc.hiprtcGetProgramLog(prog, log)
+        assert r == 0, log.value.decode()[:2000]
+        rtc.hiprtcGetCodeSize(prog, ctypes.byref(n))
+        code = ctypes.create_string_buffer(n.value)
+        rtc.hiprtcGetCode(prog, code)
+        rtc.hiprtcDestroyProgram(ctypes.byref(prog))
+        name = re.search(r"void (dqj_[0-9a-f]{16})\(", src).group(1)
+        with tempfile.NamedTemporaryFile(suffix=".co") as f:
+            f.write(code.raw)
+            f.flush()
+            dis = subprocess.run(["/opt/rocm/llvm/bin/llvm-objdump", "-d", f.name], capture_output=True, text=True).stdout
+        assert name in dis
+        assert not re.search(r"v_pk_(add|mul|fma)_f32", dis)

@@ -710,9 +710,10 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
     if (s0 < 0) s0 = 0;
     const char *T = p.dbl ? "double" : "float";
     const int R = S.R, NR = 1 << R, NS = adj ? 2 : 1;
-    // occupancy target, as for the interpreted passes (waves per SIMD)
+    // occupancy target (waves per SIMD): two while a lane holds up to 64
+    // complex64 amplitudes of one state (32 of each of two in the adjoint)
     const int rb = NR * (p.dbl ? 8 : 4);
-    const int W = adj ? (rb >= 128 ? 1 : (rb >= 64 ? 2 : 4)) : (rb >= 256 ? 1 : (rb >= 128 ? 2 : 3));
+    const int W = adj ? (rb >= 256 ? 1 : (rb >= 64 ? 2 : 4)) : (rb >= 512 ? 1 : (rb >= 128 ? 2 : 3));
     char line[256];
     std::string b;
     snprintf(line, sizeof line, "__launch_bounds__(64, %d) void @NAME@(dq::TileArgs a) {\n", W);
@@ -725,8 +726,68 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
         snprintf(line, sizeof line, "    dq::jit_fwd<%s, %d>(a, [&](auto &v, auto m, int lane) {\n", T, R);
     }
     b += line;
-    for (int64_t i = 0; i < S.nops; ++i) {
-        const TOp &o = p.ops[(size_t)(S.op0 + i)];
+    const TOp *ops = p.ops.data() + S.op0;
+    for (int64_t i = 0; i < S.nops;) {
+        // a run of one-qubit diagonal gates (the RZ of a layer and the like)
+        // becomes one product diagonal; diagonal gates commute, so their
+        // gradient terms are all taken at the start of the run
+        int64_t e = i;
+        while (e < S.nops && ops[e].kind == TK_1QDIAG) ++e;
+        if (e - i >= 2) {
+            b += "        {\n";
+            bool anyg = false;
+            for (int64_t j = i; j < e; ++j) anyg |= adj && ops[j].lslot >= 0;
+            std::vector<int> regk;   // distinct register bits of the run, in first-use order
+            for (int64_t j = i; j < e; ++j)
+                if (ops[j].q0 >= 6 && std::find(regk.begin(), regk.end(), ops[j].q0 - 6) == regk.end()) regk.push_back(ops[j].q0 - 6);
+            if (anyg) {
+                snprintf(line, sizeof line, "            %s sa_, sk_[%d];\n            dq::run_sums<%s, dq::cx<%s>, %d", T,
+                         regk.empty() ? 1 : (int)regk.size(), T, T, NR);
+                b += line;
+                for (int k : regk) b += ", " + std::to_string(k);
+                b += ">(v[0], v[1], sa_, sk_);\n";
+            }
+            for (int64_t j = i; j < e; ++j) {
+                const TOp &o = ops[j];
+                if (!adj || o.lslot < 0) continue;
+                if (o.q0 < 6) {
+                    snprintf(line, sizeof line, "            ac[%d * 64 + lane] += (double)(((lane >> %d) & 1) ? -sa_ : sa_);\n", o.lslot, o.q0);
+                } else {
+                    const size_t ri = (size_t)(std::find(regk.begin(), regk.end(), o.q0 - 6) - regk.begin());
+                    snprintf(line, sizeof line, "            ac[%d * 64 + lane] += (double)sk_[%zu];\n", o.lslot, ri);
+                }
+                b += line;
+            }
+            snprintf(line, sizeof line, "            dq::cx<%s> fl_{%s(1), %s(0)}, r_[%d];\n", T, T, T, regk.empty() ? 1 : (int)regk.size());
+            b += line;
+            std::vector<char> started(regk.size(), 0);
+            for (int64_t j = i; j < e; ++j) {
+                const TOp &o = ops[j];
+                const long long sl = (long long)(o.slot - s0);
+                if (o.q0 < 6) {
+                    snprintf(line, sizeof line, "            fl_ = dq::cmul(fl_, dq::csel(((lane >> %d) & 1) != 0, dq::ldc(m, %lld), dq::ldc(m, %lld)));\n",
+                             o.q0, sl + 3, sl);
+                } else {
+                    const size_t ri = (size_t)(std::find(regk.begin(), regk.end(), o.q0 - 6) - regk.begin());
+                    // a second gate on the same bit multiplies into that bit's ratio
+                    const std::string rv = "r_[" + std::to_string(ri) + "]";
+                    const std::string ratio = "dq::cmul(d1, dq::cconj(d0))";
+                    snprintf(line, sizeof line,
+                             "            { const auto d0 = dq::ldc(m, %lld), d1 = dq::ldc(m, %lld); fl_ = dq::cmul(fl_, d0); "
+                             "%s = %s; }\n", sl, sl + 3, rv.c_str(),
+                             (started[ri] ? "dq::cmul(" + rv + ", " + ratio + ")" : ratio).c_str());
+                    started[ri] = 1;
+                }
+                b += line;
+            }
+            snprintf(line, sizeof line, "            dq::diag_run<%s, %d, %d", T, NS, NR);
+            b += line;
+            for (int k : regk) b += ", " + std::to_string(k);
+            b += ">(v, fl_, r_);\n        }\n";
+            i = e;
+            continue;
+        }
+        const TOp &o = ops[i];
         if (adj && o.lslot >= 0) {
             snprintf(line, sizeof line, "        ac[%d * 64 + lane] += (double)dq::gen_s<%s, %d, %d, %d, %d>(v[0], v[1], lane);\n",
                      o.lslot, T, NR, o.gen, o.q0, o.q1);
@@ -735,6 +796,7 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
         snprintf(line, sizeof line, "        dq::op_s<%s, %d, %d, %d, %d, %d, %lld>(v, m, lane);\n", T, NS, NR, o.kind, o.q0,
                  o.q1, has_matrix(o.kind) ? (long long)(o.slot - s0) : 0ll);
         b += line;
+        ++i;
     }
     b += "    });\n}\n";
     return b;

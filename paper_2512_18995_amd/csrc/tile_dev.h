@@ -580,11 +580,16 @@ __device__ __forceinline__ T reg_xy_sum(const V (&v)[NR], const V (&l)[NR], bool
 template <typename T, typename V, int NR, int Q>
 __device__ __forceinline__ T lane_xy_sum(const V (&v)[NR], const V (&l)[NR], bool isY, bool hi) {
     T s = 0;
-    DQ_SF8(NR, {
-        V o = lxc<Q>(v[i]);
-        if (isY) o = csel(hi, V{-o.y, o.x}, V{o.y, -o.x});
-        s += im_dot<T>(l[i], o);
-    });
+    if (isY) {
+        // (Y v) at this lane is -i p (bit 0) or +i p (bit 1) for the partner
+        // value p, so Im(conj(l) (Y v)) = -+Re(conj(l) p): one sign per lane
+        DQ_SF8(NR, {
+            const V o = lxc<Q>(v[i]);
+            s += l[i].x * o.x + l[i].y * o.y;
+        });
+        return hi ? s : -s;
+    }
+    DQ_SF8(NR, { s += im_dot<T>(l[i], lxc<Q>(v[i])); });
     return s;
 }
 
@@ -829,6 +834,81 @@ __device__ __forceinline__ void op_s(cx<T> (&v)[NS][NR], cptr<cx<T>> m, int lane
         }
     }
 }
+
+// A run of consecutive one-qubit diagonal gates applied as one product
+// diagonal.  Per lane the factor of amplitude (lane, register i) is fl times
+// the product, over the run's register-bit gates j whose bit KS[j] is set in
+// i, of r[j] = d1_j conj(d0_j) (fl already holds every d0_j and the lane-bit
+// gates' factors; unitary diagonals have |d0| = 1).  The factors of the
+// first (up to) three register bits are built as a product tree of at most
+// eight values and applied in one multiply per amplitude; each further bit
+// multiplies its ratio into the amplitudes where it is set.
+template <int... KS> constexpr int pack_at(int j) {
+    const int ks[] = {KS..., 0};
+    return ks[j];
+}
+template <int... KS> constexpr int pack_compact(int i, int kt) {   // bit j = bit KS[j] of i, j < kt
+    const int ks[] = {KS..., 0};
+    int x = 0;
+    for (int j = 0; j < kt; ++j)
+        if ((i >> ks[j]) & 1) x |= 1 << j;
+    return x;
+}
+template <int... KS> constexpr int pack_mask(int j) {   // bits of the first j entries
+    const int ks[] = {KS..., 0};
+    int mk = 0;
+    for (int t = 0; t < j; ++t) mk |= 1 << ks[t];
+    return mk;
+}
+
+template <typename T, int NS, int NR, int... KS>
+__device__ __forceinline__ void diag_run(cx<T> (&v)[NS][NR], cx<T> fl, const cx<T> *r) {
+    using V = cx<T>;
+    constexpr int k = sizeof...(KS);
+    constexpr int kt = k < 3 ? k : 3;              // bits covered by the factor table
+    V f[1 << kt];
+    f[0] = fl;
+    static_for<0, kt>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        // f is indexed by the compacted bits of the table (bit j of the
+        // index = register bit KS[j])
+        static_for<0, (1 << j)>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            f[i | (1 << j)] = cmul(f[i], r[j]);
+        });
+    });
+    DQ_SF(NR, {
+        constexpr int c = pack_compact<KS...>(i, kt);
+        DQ_NS({ v[s_][i] = cmul(f[c], v[s_][i]); });
+    });
+    // the remaining register bits: their ratio on the amplitudes whose bit is set
+    static_for<kt, k>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int kj = pack_at<KS...>(j);
+        DQ_SF(NR, {
+            if constexpr ((i >> kj) & 1) { DQ_NS({ v[s_][i] = cmul(r[j], v[s_][i]); }); }
+        });
+    });
+}
+
+// all of a run's gradient sums in one sweep over the registers: sa = sum
+// t_i, sk[j] = sum t_i signed by register bit KS[j]
+template <typename T, typename V, int NR, int... KS>
+__device__ __forceinline__ void run_sums(const V (&v)[NR], const V (&l)[NR], T &sa, T *sk) {
+    constexpr int k = sizeof...(KS);
+    sa = 0;
+    static_for<0, k>([&](auto jc) { sk[decltype(jc)::value] = 0; });
+    DQ_SF(NR, {
+        const T t = im_dot<T>(l[i], v[i]);
+        sa += t;
+        static_for<0, k>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if constexpr ((i >> pack_at<KS...>(j)) & 1) sk[j] -= t;
+            else sk[j] += t;
+        });
+    });
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { return V{a.x, -a.y}; }
 
 // Im<lambda| P |psi> summed over this lane's registers, for the generator P
 // of a differentiable gate at compile-time positions

@@ -124,7 +124,8 @@ typedef struct {
                              time; 1: each distinct pass is compiled (hipRTC, at the plan's first
                              use on a device; code objects cached in DQ_JIT_CACHE, default
                              $HOME/.cache/dq_jit) into straight-line code with every operand
-                             position a compile-time constant */
+                             position a compile-time constant; passes longer than 2048
+                             operations x amplitudes per lane stay interpreted */
     int32_t adj_tile_bits; /* register-resident wires per tile of the adjoint sweep, which holds
                              two states: 0 = auto (min(tile bits, 4) for complex64, 3 for
                              complex128; with jit 5 and 4); 1..5 (complex128: 1..4) */

@@ -802,6 +802,11 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
     return b;
 }
 
+// operations x amplitudes per lane (per state) of the longest pass that is
+// compiled; a 32-qubit HEA pass (about 23 operations on 64 amplitudes per
+// lane) compiles in about 10 s, an 84-operation one in about a minute
+constexpr int64_t kJitMaxWork = 2048;
+
 void jit_generate(dq_plan_s &p) {
     std::map<std::string, int> index;
     auto gen = [&](Program &prog, bool adj) {
@@ -810,6 +815,9 @@ void jit_generate(dq_plan_s &p) {
         for (size_t k = 0; k < prog.steps.size(); ++k) {
             const Step &S = prog.steps[k];
             if (S.kind != ST_TILE) continue;
+            // compile time grows faster than linearly with the length of the
+            // straight-line code: longer passes stay interpreted
+            if (S.nops * (int64_t(1) << S.R) > kJitMaxWork) continue;
             int64_t s0 = 0;
             const std::string body = pass_body(p, S, adj, s0);
             auto it = index.find(body);

@@ -129,6 +129,10 @@ typedef struct {
     int32_t adj_tile_bits; /* register-resident wires per tile of the adjoint sweep, which holds
                              two states: 0 = auto (min(tile bits, 4) for complex64, 3 for
                              complex128; with jit 5 and 4); 1..5 (complex128: 1..4) */
+    int32_t low_bits;     /* states of 128 MiB and more: physical bits 3.. that every tile
+                             includes, so that each wave reads runs of 2^(3+k) amplitudes:
+                             0 = auto (bits 3 and 4 in forward passes, bit 3 in adjoint
+                             passes), 1 = none, 2 = bit 3, 3 = bits 3 and 4 */
 } dq_options;
 
 typedef struct dq_plan_s *dq_plan;

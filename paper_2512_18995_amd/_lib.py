@@ -40,7 +40,7 @@ class DqPauliTerm(ctypes.Structure):
 
 class DqOptions(ctypes.Structure):
     _fields_ = [("fusion", c_int32), ("tile_bits", c_int32), ("fold_init", c_int32), ("dense_fuse", c_int32),
-                ("jit", c_int32), ("adj_tile_bits", c_int32)]
+                ("jit", c_int32), ("adj_tile_bits", c_int32), ("low_bits", c_int32)]
 
 
 class DqPlanStats(ctypes.Structure):  # noqa: E302

@@ -135,6 +135,9 @@ std::string jit_key(const std::string &body);
 bool jit_load(const std::vector<std::string> &names, const std::vector<std::string> &srcs,
               std::vector<hipFunction_t> &out, std::string &err);
 hipError_t jit_launch(hipFunction_t f, const std::string &name, const TileArgs &a, bool adj, hipStream_t s);
+// resident single-wave workgroups of a compiled pass with `lds` bytes of
+// dynamic LDS on the current device (0 if unknown)
+int jit_resident(hipFunction_t f, size_t lds);
 hipError_t launch_tile_fwd(int dbl, const TileArgs &a, hipStream_t s);
 hipError_t launch_tile_adj(int dbl, const TileArgs &a, hipStream_t s);
 // resident single-wave workgroups of the adjoint tile kernel on the current device

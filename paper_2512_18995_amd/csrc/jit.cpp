@@ -210,6 +210,14 @@ bool jit_load(const std::vector<std::string> &names, const std::vector<std::stri
     return true;
 }
 
+int jit_resident(hipFunction_t f, size_t lds) {
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64, lds) != hipSuccess || per_cu < 1) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
+    return per_cu * cus;
+}
+
 hipError_t jit_launch(hipFunction_t f, const std::string &name, const TileArgs &a, bool adj, hipStream_t s) {
     void *args[] = {(void *)&a};
     if (adj) {

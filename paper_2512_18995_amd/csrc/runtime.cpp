@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -124,6 +125,7 @@ struct Program {
 
 struct DevData {
     std::vector<hipFunction_t> jfn;   // compiled passes, in the plan's kernel-list order
+    int jit_adj_cap = 0;              // resident waves of the slowest-filling compiled adjoint pass
     void *blob = nullptr;
     DGate *gates = nullptr;
     double2 *fixed = nullptr;
@@ -232,7 +234,13 @@ struct Planner {
     uint64_t pinned = 0;
     explicit Planner(dq_plan_s &pl, bool adj, int r) : p(pl), adjoint(adj), R(r) {
         const int64_t state_bytes = (int64_t)(p.dbl ? 16 : 8) << p.n;
-        if (R >= 2 && p.n >= R + 8 && state_bytes >= (int64_t(128) << 20)) pinned = (1ull << 3) | (1ull << 4);
+        // auto: bits 3 and 4 for the forward; bit 3 only for the adjoint,
+        // whose passes carry twice the arithmetic per byte and gain more from
+        // one more free bit (more gates per pass) than they lose in access
+        // efficiency
+        const int want = p.opt.low_bits > 0 ? p.opt.low_bits - 1 : (adj ? 1 : 2);   // physical bits 3.. to pin
+        if (want > 0 && R >= 2 && p.n >= R + 8 && state_bytes >= (int64_t(128) << 20))
+            pinned = want >= 2 ? (1ull << 3) | (1ull << 4) : (1ull << 3);
     }
 
     void gbits(int g, int *q, int &nq) const {
@@ -457,13 +465,14 @@ struct Planner {
             for (int b = 3; b < p.n; ++b)
                 if (bestS >> b & 1) freeb.push_back(b);
             std::stable_sort(freeb.begin(), freeb.end(), [&](int x, int y) { return moves[x] < moves[y]; });
-            if (pinned) {   // lane bit 3 = physical bit 3, physical bit 4 a register bit
+            if (pinned) {   // lane bit 3 = physical bit 3, physical bit 4 (if pinned) a register bit
+                const bool p4 = (pinned >> 4) & 1;
                 std::vector<int> rest;
                 for (int b : freeb)
-                    if (b != 3 && b != 4) rest.push_back(b);
+                    if (b != 3 && !(p4 && b == 4)) rest.push_back(b);
                 freeb.assign({3});
                 freeb.insert(freeb.end(), rest.begin(), rest.begin() + 2);
-                freeb.push_back(4);
+                if (p4) freeb.push_back(4);
                 freeb.insert(freeb.end(), rest.begin() + 2, rest.end());
             }
             Step st;
@@ -883,6 +892,14 @@ dq_status ensure_device(dq_plan_s &p, DevData **out) {
             (void)hipFree(dd.blob);
             return fail(DQ_ERR_INTERNAL, "%s", err.c_str());
         }
+        // the adjoint's work units per sample follow the compiled kernels'
+        // occupancy (with their accumulator LDS), not the interpreter's
+        for (size_t k = 0; k < p.adj.steps.size(); ++k) {
+            if (p.adj.jk.empty() || p.adj.jk[k] < 0) continue;
+            const size_t lds = sizeof(double) * 64 * (size_t)std::max<int64_t>(p.adj.steps[k].nls, 1);
+            const int cap = jit_resident(dd.jfn[(size_t)p.adj.jk[k]], lds);
+            if (cap > 0 && (dd.jit_adj_cap == 0 || cap < dd.jit_adj_cap)) dd.jit_adj_cap = cap;
+        }
     }
     *out = &(p.dev[dev] = dd);
     return DQ_OK;
@@ -957,6 +974,9 @@ WsLayout layout(const dq_plan_s &p, const dq_obs_s *o, int64_t batch, int per_sa
 dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, void *lam, int64_t batch,
                       const void *mats, int64_t mstride, double *partial, int wps, hipStream_t s) {
     const double SB = state_bytes(p, batch);
+    // consecutive launches of one kind share one pair of timing events, so
+    // that profiling adds no work between them
+    std::unique_ptr<ProfScope> ps;
     for (const Step &S : prog.steps) {
         hipError_t e = hipSuccess;
         const int nst = lam ? 2 : 1;   // states a per-gate sweep touches
@@ -970,9 +990,14 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
         case ST_CZ: bytes = nst * SB / 2; break;
         default: bytes = nst * 2 * SB; break;
         }
-        ProfScope ps(p, kind, nl, bytes, s);
-        ps.flops = S.flops_per_amp * (double)batch * std::ldexp(1.0, p.n) * (lam ? 2 : 1);
-        if (S.kind == ST_GRAD) ps.flops = 3.0 * (double)batch * std::ldexp(1.0, p.n);
+        if (!ps || ps->kind != kind) {
+            if (ps) ps->done();
+            ps.reset(new ProfScope(p, kind, 0, 0.0, s));
+        }
+        ps->nl += nl;
+        ps->bytes += bytes;
+        ps->flops += S.kind == ST_GRAD ? 3.0 * (double)batch * std::ldexp(1.0, p.n)
+                                       : S.flops_per_amp * (double)batch * std::ldexp(1.0, p.n) * (lam ? 2 : 1);
         switch (S.kind) {
         case ST_TILE: {
             TileArgs a{};
@@ -1019,9 +1044,12 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
             }
             break;
         }
-        ps.done();
-        if (e != hipSuccess) return fail(DQ_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            ps->done();
+            return fail(DQ_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+        }
     }
+    if (ps) ps->done();
     return DQ_OK;
 }
 
@@ -1060,8 +1088,9 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     if (ngates > (1 << 24)) return fail(DQ_ERR_OUT_OF_RANGE, "too many gates (%lld)", (long long)ngates);
     if (nparams < 0 || ndata < 0) return fail(DQ_ERR_INVALID_ARG, "negative nparams / ndata");
     if (dtype != DQ_C64 && dtype != DQ_C128) return fail(DQ_ERR_UNSUPPORTED, "dtype %d", (int)dtype);
-    dq_options o{1, 0, 1, 0, 0, 0};
+    dq_options o{1, 0, 1, 0, 0, 0, 0};
     if (opt) o = *opt;
+    if (o.low_bits < 0 || o.low_bits > 3) return fail(DQ_ERR_INVALID_ARG, "low_bits %d outside 0..3", o.low_bits);
     if (o.adj_tile_bits < 0 || o.adj_tile_bits > (dtype == DQ_C128 ? 4 : 5))
         return fail(DQ_ERR_INVALID_ARG, "adj_tile_bits %d outside 0..%d", o.adj_tile_bits, dtype == DQ_C128 ? 4 : 5);
     if (o.jit != 0 && o.jit != 1) return fail(DQ_ERR_INVALID_ARG, "jit must be 0 or 1 (got %d)", o.jit);
@@ -1423,7 +1452,8 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, 
     // round of waves covers every tile
     int wps = (int)grad_waves(*plan, batch);
     if (plan->R_adj > 0) {
-        const int cap = std::max<int64_t>(1, tile_adj_capacity(plan->dbl, plan->R_adj) / batch);
+        const int resident = d->jit_adj_cap > 0 ? d->jit_adj_cap : tile_adj_capacity(plan->dbl, plan->R_adj);
+        const int cap = std::max<int64_t>(1, resident / batch);
         wps = std::min(wps, cap);
     }
     void *psi = state;

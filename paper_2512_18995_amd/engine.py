@@ -30,7 +30,8 @@ class Plan:
     its first use on a device)."""
 
     def __init__(self, circuit, dtype: str = "c64", fusion: bool = True, tile_bits: int = 0,
-                 fold_init: bool = True, dense_fuse: int = 0, jit: bool = False, adj_tile_bits: int = 0):
+                 fold_init: bool = True, dense_fuse: int = 0, jit: bool = False, adj_tile_bits: int = 0,
+                 low_bits: int = 0):
         self.n = int(circuit.n)
         self.dtype = dtype
         self.nparams = int(circuit.n_params)
@@ -38,7 +39,7 @@ class Plan:
         self.gates = list(circuit.gates)
         arr, keep = _lib.gate_array(self.gates)
         opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, int(dense_fuse),
-                             1 if jit else 0, int(adj_tile_bits))
+                             1 if jit else 0, int(adj_tile_bits), int(low_bits))
         self.jit = bool(jit)
         h = ctypes.c_void_p()
         check(lib().dq_plan_create(ctypes.byref(h), self.n, arr, len(self.gates), self.nparams, self.ndata,

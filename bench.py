@@ -232,6 +232,7 @@ def main():
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--adj-tile-bits", type=int, default=0)
     ap.add_argument("--low-bits", type=int, default=0, help="0 auto, 1 none, 2 bit 3, 3 bits 3 and 4 in every tile")
+    ap.add_argument("--layout", choices=["auto", "canonical"], default="auto")
     ap.add_argument("--dense-fuse", type=int, default=0, choices=[0, 4, 5],
                     help="forward sweep as fused dense k-qubit blocks on the matrix cores")
     ap.add_argument("--passes", choices=["auto", "compiled", "interpreted"], default="auto",
@@ -274,7 +275,7 @@ def main():
     B = wl.batch
     jit = args.passes == "compiled" or (args.passes == "auto" and args.workload in ("cfg1", "cfg5"))
     plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits, dense_fuse=args.dense_fuse, jit=jit,
-                   adj_tile_bits=args.adj_tile_bits, low_bits=args.low_bits)
+                   adj_tile_bits=args.adj_tile_bits, low_bits=args.low_bits, layout=args.layout)
     obs = dq.Observable(c.n, wl.observables)
     params = torch.as_tensor(wl.params, dtype=torch.float64, device=dev)
     data = None if wl.data is None else torch.as_tensor(wl.data, dtype=torch.float64, device=dev)
@@ -415,7 +416,7 @@ def main():
         "plan": {"fwd_tile_passes": st["fwd_tile_passes"], "fwd_dense_blocks": st["fwd_dense_blocks"],
                  "adj_steps": st["adj_steps"],
                  "folded_gates": st["folded_gates"], "tile_bits": st["tile_bits"],
-                 "adj_tile_bits": st["adj_tile_bits"],
+                 "adj_tile_bits": st["adj_tile_bits"], "layout_swaps": st["layout_swaps"],
                  "passes": "compiled" if jit else "interpreted",
                  "compiled_kernels": len(plan.jit_sources()), "first_step_s": first_step_s},
         "checks": checks,

@@ -133,6 +133,11 @@ typedef struct {
                              includes, so that each wave reads runs of 2^(3+k) amplitudes:
                              0 = auto (bits 3 and 4 in forward passes, bit 3 in adjoint
                              passes), 1 = none, 2 = bit 3, 3 = bits 3 and 4 */
+    int32_t layout;       /* 0 (default): for states of 128 MiB and more, try relabelling physical
+                             bits 1..4 with wires spread over the register (transpositions,
+                             undone by swaps appended to the circuit, so states keep the
+                             canonical order) and keep the plan with the fewest sweeps;
+                             1: canonical bit order only */
 } dq_options;
 
 typedef struct dq_plan_s *dq_plan;
@@ -151,6 +156,8 @@ typedef struct {
     int64_t grad_gates;       /* gate occurrences that carry a gradient */
     int32_t tile_bits;        /* register bits of the forward tiles */
     int32_t adj_tile_bits;    /* register bits of the adjoint tiles */
+    int32_t layout_swaps;     /* transpositions of the chosen qubit layout (0: canonical) */
+    int32_t pad;
     /* register-tile operations of the forward program (index 0) and the
      * adjoint program (index 1) by kind: 0 dense 2x2, 1 diagonal 2x2, 2 CNOT,
      * 3 CZ, 4 two-qubit diagonal, 5 swap, 6 real 2x2, 7 RX form; [.][0][k]

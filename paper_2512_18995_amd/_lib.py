@@ -40,13 +40,13 @@ class DqPauliTerm(ctypes.Structure):
 
 class DqOptions(ctypes.Structure):
     _fields_ = [("fusion", c_int32), ("tile_bits", c_int32), ("fold_init", c_int32), ("dense_fuse", c_int32),
-                ("jit", c_int32), ("adj_tile_bits", c_int32), ("low_bits", c_int32)]
+                ("jit", c_int32), ("adj_tile_bits", c_int32), ("low_bits", c_int32), ("layout", c_int32)]
 
 
 class DqPlanStats(ctypes.Structure):  # noqa: E302
     _fields_ = [("nqubits", c_int32), ("dtype", c_int32), ("ngates", c_int64), ("fwd_steps", c_int64),
                 ("fwd_tile_passes", c_int64), ("fwd_dense_blocks", c_int64), ("adj_steps", c_int64),
-                ("folded_gates", c_int64), ("grad_gates", c_int64), ("tile_bits", c_int32), ("adj_tile_bits", c_int32),
+                ("folded_gates", c_int64), ("grad_gates", c_int64), ("tile_bits", c_int32), ("adj_tile_bits", c_int32), ("layout_swaps", c_int32), ("pad", c_int32),
                 ("tile_ops", ((c_int64 * 8) * 2) * 2)]
 
 

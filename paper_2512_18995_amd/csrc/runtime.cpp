@@ -158,6 +158,8 @@ struct dq_plan_s {
     Program fwd_full, fwd_fold, adj;
     bool has_fold = false;
     std::vector<std::string> jnames, jsrcs;   // compiled passes: kernel names and sources
+    int64_t user_gates = 0;                    // gates given by the caller (the layout may append swaps)
+    int32_t layout_swaps = 0;
     std::vector<int64_t> fold_off;      // per physical bit: slot offset of the folded column, -1 none
     int64_t folded_gates = 0;
     int R_fwd = 0, R_adj = 0;
@@ -847,6 +849,84 @@ void jit_generate(dq_plan_s &p) {
     gen(p.adj, true);
 }
 
+// ---------------------------------------------------------------- qubit layout
+// Physical bits 0..2 (and, in large states, 3 and 4) are in every tile, so
+// the wires that sit there cost nothing to include in a pass.  When those
+// wires are adjacent in the circuit's entangling structure (the ring's last
+// five wires in wire order), every pass must re-include a linking wire; the
+// search below relabels physical bits 1..4 with four wires spread evenly over
+// the register (a set of transpositions), plans each candidate, and keeps the
+// one with the fewest state sweeps (forward steps x 2 + adjoint steps x 4).
+// The same transpositions are appended as SWAP gates, so the state handed back
+// keeps the canonical order; the adjoint undoes them first.
+double plan_cost(const dq_plan_s &p) {
+    const Program &f = p.has_fold ? p.fwd_fold : p.fwd_full;
+    return 2.0 * (double)f.steps.size() + 4.0 * (double)p.adj.steps.size();
+}
+
+dq_plan_s *plan_clone_base(const dq_plan_s &p) {
+    auto *q = new dq_plan_s();
+    q->n = p.n;
+    q->dbl = p.dbl;
+    q->opt = p.opt;
+    q->nparams = p.nparams;
+    q->ndata = p.ndata;
+    q->fixed = p.fixed;
+    q->user_gates = p.user_gates;
+    return q;
+}
+
+dq_plan_s *search_layout(dq_plan_s *p) {
+    const int64_t state_bytes = (int64_t)(p->dbl ? 16 : 8) << p->n;
+    if (!p->opt.fusion || p->R_fwd < 2 || p->n < 16 || state_bytes < (int64_t(128) << 20)) return p;
+    const std::vector<DGate> base(p->gates.begin(), p->gates.begin() + p->user_gates);
+    double best = plan_cost(*p);
+    // k of the low bits 4, 3, .. (those pinned last first) move to k wires
+    // spaced d apart from offset o
+    for (int k : {3, 4})
+    for (int d : {p->n / 3, p->n / 4, p->n / 5}) {
+        if (d < 2) continue;
+        for (int o = 0; o < d; ++o) {
+            int tgt[4], lows[4];
+            bool ok = true;
+            for (int j = 0; j < k; ++j) {
+                tgt[j] = o + j * d;
+                lows[j] = 1 + j;
+                ok &= tgt[j] >= 5 && tgt[j] < p->n;
+            }
+            if (!ok) continue;
+            int perm[64];
+            for (int b = 0; b < p->n; ++b) perm[b] = b;
+            for (int j = 0; j < k; ++j) {
+                perm[lows[j]] = tgt[k - 1 - j];
+                perm[tgt[k - 1 - j]] = lows[j];
+            }
+            dq_plan_s *q = plan_clone_base(*p);
+            q->gates = base;
+            for (DGate &g : q->gates)
+                for (int i = 0; i < g.nq; ++i) g.bits[i] = perm[g.bits[i]];
+            for (int j = 0; j < k; ++j) {   // back to the canonical order at the end
+                DGate sw{};
+                sw.op = OP_SWAP;
+                sw.nq = 2;
+                sw.bits[0] = tgt[k - 1 - j];
+                sw.bits[1] = lows[j];
+                sw.src = SRC_NONE;
+                q->gates.push_back(sw);
+            }
+            q->layout_swaps = k;
+            if (build_plan(*q) == DQ_OK && plan_cost(*q) < best) {
+                best = plan_cost(*q);
+                delete p;
+                p = q;
+            } else {
+                delete q;
+            }
+        }
+    }
+    return p;
+}
+
 dq_status ensure_device(dq_plan_s &p, DevData **out) {
     int dev = 0;
     DQ_HIP(hipGetDevice(&dev));
@@ -1088,9 +1168,10 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     if (ngates > (1 << 24)) return fail(DQ_ERR_OUT_OF_RANGE, "too many gates (%lld)", (long long)ngates);
     if (nparams < 0 || ndata < 0) return fail(DQ_ERR_INVALID_ARG, "negative nparams / ndata");
     if (dtype != DQ_C64 && dtype != DQ_C128) return fail(DQ_ERR_UNSUPPORTED, "dtype %d", (int)dtype);
-    dq_options o{1, 0, 1, 0, 0, 0, 0};
+    dq_options o{1, 0, 1, 0, 0, 0, 0, 0};
     if (opt) o = *opt;
     if (o.low_bits < 0 || o.low_bits > 3) return fail(DQ_ERR_INVALID_ARG, "low_bits %d outside 0..3", o.low_bits);
+    if (o.layout != 0 && o.layout != 1) return fail(DQ_ERR_INVALID_ARG, "layout must be 0 or 1 (got %d)", o.layout);
     if (o.adj_tile_bits < 0 || o.adj_tile_bits > (dtype == DQ_C128 ? 4 : 5))
         return fail(DQ_ERR_INVALID_ARG, "adj_tile_bits %d outside 0..%d", o.adj_tile_bits, dtype == DQ_C128 ? 4 : 5);
     if (o.jit != 0 && o.jit != 1) return fail(DQ_ERR_INVALID_ARG, "jit must be 0 or 1 (got %d)", o.jit);
@@ -1161,11 +1242,13 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
         }
         p->gates.push_back(D);
     }
+    p->user_gates = (int64_t)p->gates.size();
     dq_status st = build_plan(*p);
     if (st != DQ_OK) {
         delete p;
         return st;
     }
+    if (o.layout == 0) p = search_layout(p);
     if (o.jit) jit_generate(*p);
     *out = p;
     return ok();
@@ -1190,7 +1273,7 @@ dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) {
     dq_plan_stats s{};
     s.nqubits = plan->n;
     s.dtype = plan->dbl ? DQ_C128 : DQ_C64;
-    s.ngates = (int64_t)plan->gates.size();
+    s.ngates = plan->user_gates;
     const Program &f = plan->has_fold ? plan->fwd_fold : plan->fwd_full;
     s.fwd_steps = (int64_t)f.steps.size() + (plan->has_fold ? 1 : 0);
     s.fwd_tile_passes = f.tile_passes;
@@ -1200,6 +1283,7 @@ dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) {
     s.grad_gates = plan->ngrad;
     s.tile_bits = plan->R_fwd;
     s.adj_tile_bits = plan->R_adj;
+    s.layout_swaps = plan->layout_swaps;
     for (int which = 0; which < 2; ++which) {
         const Program &prog = which ? plan->adj : f;
         for (const Step &S : prog.steps) {

@@ -31,7 +31,7 @@ class Plan:
 
     def __init__(self, circuit, dtype: str = "c64", fusion: bool = True, tile_bits: int = 0,
                  fold_init: bool = True, dense_fuse: int = 0, jit: bool = False, adj_tile_bits: int = 0,
-                 low_bits: int = 0):
+                 low_bits: int = 0, layout: str = "auto"):
         self.n = int(circuit.n)
         self.dtype = dtype
         self.nparams = int(circuit.n_params)
@@ -39,7 +39,8 @@ class Plan:
         self.gates = list(circuit.gates)
         arr, keep = _lib.gate_array(self.gates)
         opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, int(dense_fuse),
-                             1 if jit else 0, int(adj_tile_bits), int(low_bits))
+                             1 if jit else 0, int(adj_tile_bits), int(low_bits),
+                             {"auto": 0, "canonical": 1}[layout])
         self.jit = bool(jit)
         h = ctypes.c_void_p()
         check(lib().dq_plan_create(ctypes.byref(h), self.n, arr, len(self.gates), self.nparams, self.ndata,
@@ -63,7 +64,7 @@ class Plan:
     def stats(self) -> dict:
         s = _lib.DqPlanStats()
         check(lib().dq_plan_get_stats(self._h, ctypes.byref(s)), "dq_plan_get_stats")
-        out = {k: getattr(s, k) for k, _ in _lib.DqPlanStats._fields_ if k != "tile_ops"}
+        out = {k: getattr(s, k) for k, _ in _lib.DqPlanStats._fields_ if k not in ("tile_ops", "pad")}
         kinds = ["1q", "1q_diag", "cnot", "cz", "2q_diag", "swap", "1q_real", "1q_rx"]
         for w, prog in enumerate(("fwd", "adj")):
             for where, name in enumerate(("lane", "reg")):

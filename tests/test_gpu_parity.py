@@ -373,3 +373,27 @@ def test_uneven_full_config_multi_equals_single_plans():
             want = oracle.expvals(n, oracle.state(it.circuit, it.params), it.observables)[0]
             normwise([e1], [want], 1e-5, 1e-6, "circuit %d expval vs oracle" % c)
     assert not bad, "multi vs single plan differ (c, n, gates, E_multi, E_single, |dg|, finite): %s" % bad[:8]
+
+
+@pytest.mark.parametrize("jit", [False, True], ids=["interpreted", "compiled"])
+def test_layout_search_keeps_canonical_order(jit):
+    """For a large state the planner may relabel physical bits and append
+    the undoing swaps: the state handed back stays in the canonical order,
+    and expectations and gradients equal those of the canonical plan."""
+    n = 24
+    w = W.config(5, n=n, layers=4)
+    obs = dq.Observable(n, w.observables)
+    out = {}
+    for lay in ("auto", "canonical"):
+        plan = dq.Plan(w.circuit, "c64", jit=jit, layout=lay)
+        assert (plan.stats()["layout_swaps"] > 0) == (lay == "auto")
+        st = plan.state(1, DEV)
+        p = t64(w.params)
+        dq.apply_circuit(plan, st, p, None, from_zero=True)
+        S = st.cpu().numpy()[0]
+        E = dq.expval(plan, obs, st).cpu().numpy()
+        g, _ = dq.adjoint_grad(plan, obs, st, p, None, t64(np.ones((1, 1))))
+        out[lay] = (S, E, g.cpu().numpy())
+    assert_state(out["auto"][0], out["canonical"][0].astype(np.complex128), "c64", 2 * len(w.circuit.gates), "state")
+    normwise(out["auto"][1], out["canonical"][1], RTOL["c64"], 1e-7, "expval")
+    normwise(out["auto"][2], out["canonical"][2], RTOL["c64"], 1e-7, "gradient")

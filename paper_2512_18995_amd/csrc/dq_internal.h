@@ -153,11 +153,22 @@ hipError_t launch_grad_gate(int dbl, const void *psi, const void *lam, int32_t n
 hipError_t launch_grad_final(const double *partial, int64_t batch, int32_t wps, int32_t ngrad,
                              const int64_t *csr_off, const int32_t *csr_g, const double *csr_f,
                              int64_t nout, int32_t per_sample, double *out, hipStream_t s);
-hipError_t launch_expval(int dbl, const void *st, int32_t n, int64_t batch, const DGroup *groups,
-                         int32_t ngroups, const DTerm *terms, int32_t nterms, int32_t nobs,
-                         double *partial, int32_t eb, double *out, hipStream_t s);
+// observables at most the diagonal expectation kernel sums at once
+constexpr int ZD_MAXOBS = 8;
+// blocks of the diagonal expectation kernel per sample (4 waves of
+// 2048-amplitude tiles each), for n >= 11
+inline int zdiag_blocks(int n) {
+    if (n < 11) return 1;
+    const int64_t q = (int64_t(1) << (n - 11)) / 4;
+    return (int)(q < 1 ? 1 : (q < 1024 ? q : 1024));
+}
+// expectations; terms dt0..dt1 (group 0, X-free) go through the diagonal
+// kernel into dpart ([batch][blocks][nobs] doubles) when dt0 < dt1
+hipError_t launch_expval(int dbl, const void *st, int32_t n, int64_t batch, const DGroup *groups, int32_t ngroups,
+                         const DTerm *terms, int32_t nterms, int32_t nobs, double *partial, int32_t eb, double *out,
+                         int32_t dt0, int32_t dt1, double *dpart, hipStream_t s);
 hipError_t launch_lambda(int dbl, const void *psi, void *lam, int32_t n, int64_t batch, const DGroup *groups,
-                         int32_t ngroups, const DTerm *terms, const double *grad_out, int32_t nobs,
+                         int32_t ngroups, const DTerm *terms, const double *grad_out, int32_t nobs, int32_t dt0, int32_t dt1,
                          hipStream_t s);
 
 }  // namespace dq

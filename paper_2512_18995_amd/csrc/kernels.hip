@@ -230,6 +230,51 @@ __global__ __launch_bounds__(256) void k_init_product(cx<T> *st, int n, const cx
     }
 }
 
+// The same state for n >= 16: a block writes 2^16 consecutive amplitudes whose
+// bits 16.. are fixed (one product per block), bits 8..15 index a 256-entry
+// product table in LDS and bits 0..7 are this thread's (one product per
+// thread), so each amplitude costs one complex multiply.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_product_tab(cx<T> *st, int n, const cx<T> *mats, int64_t mstride,
+                                                          const int64_t *fold_off) {
+    __shared__ double2 u[64][2];
+    __shared__ double2 tab[256];
+    const int64_t b = blockIdx.y;
+    const int t = threadIdx.x;
+    if (t < n) {
+        const int64_t off = fold_off[t];
+        if (off < 0) {
+            u[t][0] = double2{1.0, 0.0};
+            u[t][1] = double2{0.0, 0.0};
+        } else {
+            const cx<T> *m = mats + b * mstride + off;
+            u[t][0] = double2{(double)m[0].x, (double)m[0].y};
+            u[t][1] = double2{(double)m[2].x, (double)m[2].y};
+        }
+    }
+    __syncthreads();
+    auto mul = [](double2 a, double2 c) { return double2{a.x * c.x - a.y * c.y, a.x * c.y + a.y * c.x}; };
+    {
+        double2 f{1.0, 0.0};
+        for (int k = 0; k < 8; ++k) f = mul(f, u[8 + k][(t >> k) & 1]);
+        tab[t] = f;
+    }
+    double2 lo{1.0, 0.0};
+    for (int k = 0; k < 8; ++k) lo = mul(lo, u[k][(t >> k) & 1]);
+    __syncthreads();
+    const int64_t nblk = int64_t(1) << (n - 16);
+    cx<T> *p = st + (b << n);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        double2 q = lo;
+        for (int k = 16; k < n; ++k) q = mul(q, u[k][(blk >> (k - 16)) & 1]);
+        cx<T> *pb = p + (blk << 16);
+        for (int r = 0; r < 256; ++r) {
+            const double2 a = mul(q, tab[r]);
+            pb[(r << 8) + t] = cx<T>{(T)a.x, (T)a.y};
+        }
+    }
+}
+
 // ============================================================ plain per-gate sweeps
 // Each thread keeps SWEEP_U pairs in flight: all loads are issued before the
 // first update, so a wave has 2 x SWEEP_U independent 512-byte (complex64)
@@ -593,7 +638,7 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_expval_part(const cx<T> *st, int n, const DGroup *groups, int ngroups,
+__global__ __launch_bounds__(256) void k_expval_part(const cx<T> *st, int n, const DGroup *groups, int g0, int ngroups,
                                                      const DTerm *terms, int nterms, double *partial, int eb) {
     __shared__ double red[4][2 * EXP_TM];
     const int64_t b = blockIdx.y;
@@ -602,7 +647,7 @@ __global__ __launch_bounds__(256) void k_expval_part(const cx<T> *st, int n, con
     const cptr<DGroup> gp = to_const(groups);
     const cptr<DTerm> tp = to_const(terms);
     double *row = partial + (b * eb + blockIdx.x) * (int64_t)nterms * 2;   // this block's [nterms][2]
-    for (int g = 0; g < ngroups; ++g) {
+    for (int g = g0; g < ngroups; ++g) {
         const uint64_t x = gp[g].xmask;
         const int t0 = gp[g].t0, t1 = gp[g].t1;
         for (int c0 = t0; c0 < t1; c0 += EXP_TM) {
@@ -613,16 +658,88 @@ __global__ __launch_bounds__(256) void k_expval_part(const cx<T> *st, int n, con
     }
 }
 
+// The X-free group (diagonal observables) for n >= 11: per amplitude j the
+// weight d_o(j) = sum_{t in o} w_t (-1)^{|j & z_t|} (w_t real: no Y without X).
+// A wave owns tiles of 2048 consecutive amplitudes, lane l holding
+// j = 2048 tile + 64 i + l for registers i = 0..31 (each load instruction
+// reads 512 contiguous bytes).  A term's sign is the product of a tile part
+// (uniform), a lane part and a register part (bits 6..10 of j); the first two
+// are taken once per tile and term, and terms whose mask misses bits 6..10
+// weigh all 32 registers alike.  Terms are ordered by observable.
+//   EXPVAL: partial[b][block][o] = sum_j d_o(j) |psi_j|^2 over the block's tiles
+//   LAMBDA: lam_j = (sum_o g[b,o] d_o(j)) psi_j
+template <typename T, bool LAMBDA>
+__global__ __launch_bounds__(256) void k_zdiag(const cx<T> *psi, cx<T> *lam, int n, const DTerm *terms, int t0, int t1,
+                                              const double *gout, int nobs, double *partial) {
+    __shared__ double red[4][ZD_MAXOBS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t b = blockIdx.y;
+    const cptr<DTerm> tp = to_const(terms);
+    const cx<T> *p = psi + (b << n);
+    double acc[ZD_MAXOBS];
+    for (int o = 0; o < ZD_MAXOBS; ++o) acc[o] = 0.0;
+    const int64_t ntiles = int64_t(1) << (n - 11);
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const uint64_t base = (uint64_t)tile << 11;
+        cx<T> v[32];
+        DQ_SF(32, { v[i] = p[base + 64 * i + lane]; });
+        T d[32];
+        DQ_SF(32, { d[i] = T(0); });
+        int t = t0;
+        while (t < t1) {
+            const int o = tp[t].obs;
+            T e[32];
+            DQ_SF(32, { e[i] = T(0); });
+            T ec = 0;   // terms that weigh every register alike
+            for (; t < t1 && tp[t].obs == o; ++t) {
+                const uint64_t z = tp[t].zmask;
+                const int hs = __popcll(base & z) & 1, ls = __popc((unsigned)lane & (unsigned)z) & 1;
+                const T c = ((hs ^ ls) ? T(-1) : T(1)) * (T)tp[t].wr;
+                const unsigned zr = (unsigned)(z >> 6) & 31u;
+                if (zr == 0) {
+                    ec += c;
+                } else {
+                    DQ_SF(32, { e[i] += (__popc((unsigned)i & zr) & 1) ? -c : c; });
+                }
+            }
+            if (LAMBDA) {
+                const T g = (T)gout[b * nobs + o];
+                DQ_SF(32, { d[i] += g * (e[i] + ec); });
+            } else if (o < ZD_MAXOBS) {
+                T s = 0;
+                DQ_SF(32, { s += (e[i] + ec) * (v[i].x * v[i].x + v[i].y * v[i].y); });
+                acc[o] += (double)s;
+            }
+        }
+        if (LAMBDA) {
+            cx<T> *q = lam + (b << n);
+            DQ_SF(32, { q[base + 64 * i + lane] = cx<T>{d[i] * v[i].x, d[i] * v[i].y}; });
+        }
+    }
+    if (!LAMBDA) {
+        for (int o = 0; o < nobs && o < ZD_MAXOBS; ++o) {
+            const double x = wave_sum(acc[o]);
+            if (lane == 0) red[wv][o] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < nobs && threadIdx.x < ZD_MAXOBS)
+            partial[(b * gridDim.x + blockIdx.x) * nobs + threadIdx.x] =
+                (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    }
+}
+
 __global__ void k_expval_final(const double *partial, int64_t batch, int eb, const DTerm *terms, int nterms,
-                               int nobs, double *out) {
+                               int nobs, double *out, int skip0, int skip1, const double *dpart, int deb) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= batch * nobs) return;
     const int64_t b = i / nobs;
     const int o = (int)(i % nobs);
     double e = 0.0;
+    if (dpart)   // the X-free group, summed by k_zdiag
+        for (int k = 0; k < deb; ++k) e += dpart[(b * deb + k) * nobs + o];
     for (int t = 0; t < nterms; ++t) {
         const DTerm tm = terms[t];
-        if (tm.obs != o) continue;
+        if (tm.obs != o || (t >= skip0 && t < skip1)) continue;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < eb; ++k) {
             sr += partial[((b * eb + k) * (int64_t)nterms + t) * 2];
@@ -637,7 +754,7 @@ __global__ void k_expval_final(const double *partial, int64_t batch, int eb, con
 // (for the X-free group the terms collapse into one factor d(j) psi_j)
 template <typename T>
 __global__ __launch_bounds__(256) void k_lambda(const cx<T> *psi, cx<T> *lam, int n, int64_t total, const DGroup *groups,
-                                                int ngroups, const DTerm *terms, const double *gout, int nobs) {
+                                                int g0, int ngroups, const DTerm *terms, const double *gout, int nobs, bool add) {
     const int64_t mask = (int64_t(1) << n) - 1;
     const cptr<DGroup> gp = to_const(groups);
     const cptr<DTerm> tp = to_const(terms);
@@ -647,7 +764,7 @@ __global__ __launch_bounds__(256) void k_lambda(const cx<T> *psi, cx<T> *lam, in
         const int64_t b = i >> n, j = i & mask;
         const cx<T> *p = psi + (b << n);
         double ar = 0.0, ai = 0.0;
-        for (int g = 0; g < ngroups; ++g) {
+        for (int g = g0; g < ngroups; ++g) {
             const uint64_t x = gp[g].xmask;
             const int t0 = gp[g].t0, t1 = gp[g].t1;
             const int64_t jx = j ^ (int64_t)x;
@@ -664,6 +781,10 @@ __global__ __launch_bounds__(256) void k_lambda(const cx<T> *psi, cx<T> *lam, in
             const double ox = (double)o.x, oy = (double)o.y;
             ar += dr * ox - di * oy;
             ai += dr * oy + di * ox;
+        }
+        if (add) {
+            ar += (double)lam[i].x;
+            ai += (double)lam[i].y;
         }
         lam[i] = cx<T>{(T)ar, (T)ai};
     }
@@ -733,6 +854,17 @@ hipError_t launch_copy(int dbl, void *dst, const void *src, int64_t count, hipSt
 hipError_t launch_init_product(int dbl, void *st, int32_t n, int64_t batch, const void *mats, int64_t mstride,
                                const int64_t *fold_off, hipStream_t s) {
     const int64_t N = int64_t(1) << n;
+    if (n >= 16) {
+        const int64_t nblk = N >> 16;
+        dim3 grid((unsigned)(nblk < 4096 ? nblk : 4096), (unsigned)batch);
+        if (dbl)
+            hipLaunchKernelGGL(k_init_product_tab<double>, grid, dim3(256), 0, s, (C128 *)st, n, (const C128 *)mats,
+                               mstride, fold_off);
+        else
+            hipLaunchKernelGGL(k_init_product_tab<float>, grid, dim3(256), 0, s, (C64 *)st, n, (const C64 *)mats,
+                               mstride, fold_off);
+        DQ_LAUNCH_RET;
+    }
     dim3 grid(grid_for(N, 256, 8192), (unsigned)batch);
     if (dbl)
         hipLaunchKernelGGL(k_init_product<double>, grid, dim3(256), 0, s, (C128 *)st, n, (const C128 *)mats,
@@ -871,31 +1003,60 @@ hipError_t launch_grad_final(const double *partial, int64_t batch, int32_t wps, 
 
 hipError_t launch_expval(int dbl, const void *st, int32_t n, int64_t batch, const DGroup *groups, int32_t ngroups,
                          const DTerm *terms, int32_t nterms, int32_t nobs, double *partial, int32_t eb, double *out,
-                         hipStream_t s) {
-    dim3 g((unsigned)eb, (unsigned)batch);
-    if (dbl)
-        hipLaunchKernelGGL(k_expval_part<double>, g, dim3(256), 0, s, (const C128 *)st, n, groups, ngroups, terms,
-                           nterms, partial, eb);
-    else
-        hipLaunchKernelGGL(k_expval_part<float>, g, dim3(256), 0, s, (const C64 *)st, n, groups, ngroups, terms,
-                           nterms, partial, eb);
+                         int32_t dt0, int32_t dt1, double *dpart, hipStream_t s) {
+    // the X-free group (terms dt0..dt1, group 0) by k_zdiag when dt0 < dt1
+    const bool zd = dt0 < dt1;
+    const int deb = zd ? zdiag_blocks(n) : 0;
+    if (zd) {
+        dim3 g((unsigned)deb, (unsigned)batch);
+        if (dbl)
+            hipLaunchKernelGGL((k_zdiag<double, false>), g, dim3(256), 0, s, (const C128 *)st, (C128 *)nullptr, n, terms,
+                               dt0, dt1, (const double *)nullptr, nobs, dpart);
+        else
+            hipLaunchKernelGGL((k_zdiag<float, false>), g, dim3(256), 0, s, (const C64 *)st, (C64 *)nullptr, n, terms,
+                               dt0, dt1, (const double *)nullptr, nobs, dpart);
+    }
+    const int g0 = zd ? 1 : 0;
+    if (ngroups > g0) {
+        dim3 g((unsigned)eb, (unsigned)batch);
+        if (dbl)
+            hipLaunchKernelGGL(k_expval_part<double>, g, dim3(256), 0, s, (const C128 *)st, n, groups, g0, ngroups, terms,
+                               nterms, partial, eb);
+        else
+            hipLaunchKernelGGL(k_expval_part<float>, g, dim3(256), 0, s, (const C64 *)st, n, groups, g0, ngroups, terms,
+                               nterms, partial, eb);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t total = batch * nobs;
     hipLaunchKernelGGL(k_expval_final, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, partial, batch, eb,
-                       terms, nterms, nobs, out);
+                       terms, nterms, nobs, out, zd ? dt0 : 0, zd ? dt1 : 0, zd ? (const double *)dpart : nullptr, deb);
     DQ_LAUNCH_RET;
 }
 
 hipError_t launch_lambda(int dbl, const void *psi, void *lam, int32_t n, int64_t batch, const DGroup *groups,
-                         int32_t ngroups, const DTerm *terms, const double *grad_out, int32_t nobs, hipStream_t s) {
+                         int32_t ngroups, const DTerm *terms, const double *grad_out, int32_t nobs, int32_t dt0, int32_t dt1,
+                         hipStream_t s) {
     const int64_t total = batch << n;
+    const bool zd = dt0 < dt1;   // the X-free group (terms dt0..dt1, group 0) by k_zdiag
+    if (zd) {
+        const int64_t q = (int64_t(1) << (n - 11)) / 4;
+        dim3 g((unsigned)(q < 1 ? 1 : (q < 4096 ? q : 4096)), (unsigned)batch);
+        if (dbl)
+            hipLaunchKernelGGL((k_zdiag<double, true>), g, dim3(256), 0, s, (const C128 *)psi, (C128 *)lam, n, terms,
+                               dt0, dt1, grad_out, nobs, (double *)nullptr);
+        else
+            hipLaunchKernelGGL((k_zdiag<float, true>), g, dim3(256), 0, s, (const C64 *)psi, (C64 *)lam, n, terms,
+                               dt0, dt1, grad_out, nobs, (double *)nullptr);
+        if (ngroups <= 1) DQ_LAUNCH_RET;
+    }
+    const int g0 = zd ? 1 : 0;
     if (dbl)
         hipLaunchKernelGGL(k_lambda<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C128 *)psi,
-                           (C128 *)lam, n, total, groups, ngroups, terms, grad_out, nobs);
+                           (C128 *)lam, n, total, groups, g0, ngroups, terms, grad_out, nobs, zd);
     else
         hipLaunchKernelGGL(k_lambda<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C64 *)psi,
-                           (C64 *)lam, n, total, groups, ngroups, terms, grad_out, nobs);
+                           (C64 *)lam, n, total, groups, g0, ngroups, terms, grad_out, nobs, zd);
     DQ_LAUNCH_RET;
 }
 

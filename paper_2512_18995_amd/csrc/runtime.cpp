@@ -1027,8 +1027,18 @@ int64_t grad_waves(const dq_plan_s &p, int64_t batch) {
 }
 
 struct WsLayout {
-    size_t mats = 0, expv = 0, lam = 0, keep = 0, part = 0, total = 0;
+    size_t mats = 0, expv = 0, zdp = 0, lam = 0, keep = 0, part = 0, total = 0;
 };
+
+// terms [t0, t1) of the X-free group when the diagonal kernel takes it
+// (group 0 has xmask 0 and the state is at least one 2048-amplitude tile)
+bool zdiag_range(const dq_plan_s &p, const dq_obs_s &o, int32_t &t0, int32_t &t1) {
+    t0 = t1 = 0;
+    if (p.n < 11 || o.groups.empty() || o.groups[0].xmask != 0) return false;
+    t0 = o.groups[0].t0;
+    t1 = o.groups[0].t1;
+    return t0 < t1;
+}
 
 WsLayout layout(const dq_plan_s &p, const dq_obs_s *o, int64_t batch, int per_sample, int grad) {
     WsLayout L;
@@ -1039,6 +1049,8 @@ WsLayout layout(const dq_plan_s &p, const dq_obs_s *o, int64_t batch, int per_sa
     off = align256(off + (size_t)bm * (size_t)std::max<int64_t>(p.block, 1) * amp);
     L.expv = off;
     if (o) off = align256(off + (size_t)batch * expval_blocks(p.n, batch) * std::max<size_t>(o->terms.size(), 1) * 16);
+    L.zdp = off;
+    if (o) off = align256(off + (size_t)batch * zdiag_blocks(p.n) * o->nobs * 8);
     L.lam = off;
     const size_t sbytes = (size_t)batch * ((size_t)1 << p.n) * amp;
     if (grad) off = align256(off + sbytes);
@@ -1395,7 +1407,10 @@ dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms
             }
             all.push_back({px, pz, T.coef, ob});
         }
-    std::stable_sort(all.begin(), all.end(), [](const Tm &a, const Tm &b) { return a.x < b.x; });
+    // grouped by X mask (one pass over the state per group), and within a
+    // group by observable (the diagonal kernel sums one observable's run)
+    std::stable_sort(all.begin(), all.end(),
+                     [](const Tm &a, const Tm &b) { return a.x != b.x ? a.x < b.x : a.obs < b.obs; });
     for (size_t i = 0; i < all.size(); ++i) {
         if (o->groups.empty() || o->groups.back().xmask != all[i].x)
             o->groups.push_back(DGroup{all[i].x, (int32_t)i, (int32_t)i});
@@ -1495,10 +1510,12 @@ dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, 
     const DTerm *t = nullptr;
     if ((st = ensure_obs(*obs, &g, &t)) != DQ_OK) return st;
     const int eb = (int)expval_blocks(plan->n, batch);
+    int32_t dt0, dt1;
+    if (!zdiag_range(*plan, *obs, dt0, dt1) || obs->nobs > ZD_MAXOBS) dt0 = dt1 = 0;
     ProfScope pe(*plan, DQ_PROF_EXPVAL, 2, state_bytes(*plan, batch) * (double)obs->groups.size(), (hipStream_t)stream);
     hipError_t e = launch_expval(plan->dbl, state, plan->n, batch, g, (int32_t)obs->groups.size(), t,
-                                 (int32_t)obs->terms.size(), obs->nobs, (double *)((char *)ws + L.expv), eb, out,
-                                 (hipStream_t)stream);
+                                 (int32_t)obs->terms.size(), obs->nobs, (double *)((char *)ws + L.expv), eb, out, dt0,
+                                 dt1, (double *)((char *)ws + L.zdp), (hipStream_t)stream);
     pe.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "expval: %s", hipGetErrorString(e));
     return ok();
@@ -1556,8 +1573,11 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, 
                        mats, plan->block, bm, s);
     pp.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
+    int32_t dt0, dt1;
+    zdiag_range(*plan, *obs, dt0, dt1);
     ProfScope pl(*plan, DQ_PROF_LAMBDA, 1, 2 * SB, s);
-    e = launch_lambda(plan->dbl, psi, lam, plan->n, batch, g, (int32_t)obs->groups.size(), t, grad_out, obs->nobs, s);
+    e = launch_lambda(plan->dbl, psi, lam, plan->n, batch, g, (int32_t)obs->groups.size(), t, grad_out, obs->nobs, dt0,
+                      dt1, s);
     pl.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "lambda: %s", hipGetErrorString(e));
     if ((st = run_program(*plan, *d, plan->adj, psi, lam, batch, mats, mstride, partial, wps, s)) != DQ_OK) return st;
@@ -1910,9 +1930,11 @@ dq_status dq_multi_adjoint_grad(dq_multi m, void *states, const double *params, 
         void *lam = w + m->ws_off[c] + m->lay[c].lam;
         hipError_t e = launch_prepare(p->dbl, d.gates, d.fixed, d.slots + p->adj.slot_lo,
                                       (int32_t)(p->adj.slot_hi - p->adj.slot_lo), pc, 0, nullptr, 0, mats, p->block, 1, s);
+        int32_t dt0, dt1;
+        zdiag_range(*p, *m->obs[c], dt0, dt1);
         if (e == hipSuccess)
             e = launch_lambda(p->dbl, sc, lam, p->n, 1, g, (int32_t)m->obs[c]->groups.size(), t, grad_out + m->out_off[c],
-                              m->obs[c]->nobs, s);
+                              m->obs[c]->nobs, dt0, dt1, s);
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi adjoint seed: %s", hipGetErrorString(e));
     }
     for (size_t k = 0; k < m->adj.size(); ++k) {

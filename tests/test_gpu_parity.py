@@ -87,6 +87,62 @@ def test_random_circuit_states_and_expvals(dtype, fusion, n, batch, per_sample):
                  "expval sample %d" % b)
 
 
+def _diag_sums(rng, n, nobs, nterms):
+    """Sums whose X-free terms take the diagonal-observable kernel: Z on
+    random wires, on wires that are bits 6..10 of an amplitude index only
+    (the register part of its 2048-amplitude tile), on the other wires only,
+    an identity term, and in every other observable an X-carrying term that
+    takes the general path beside them; observables are interleaved term by
+    term in the list handed over."""
+    def zs(wires):
+        s = ["I"] * n
+        for w in wires:
+            s[int(w)] = "Z"
+        return "".join(s)
+    mid = [n - 1 - b for b in range(6, 11)]
+    rest = [w for w in range(n) if w not in mid]
+    obs = [[] for _ in range(nobs)]
+    for k in range(nterms):
+        for o in range(nobs):
+            pick = (k + o) % 3
+            pool = range(n) if pick == 0 else (mid if pick == 1 else rest)
+            wires = rng.choice(list(pool), size=int(rng.integers(1, 4)), replace=False)
+            obs[o].append((float(rng.standard_normal()), zs(wires)))
+    obs[0].append((0.25, "I" * n))
+    for o in range(1, nobs, 2):
+        obs[o].append((0.7, "X" + "I" * (n - 2) + "Z"))
+    return obs
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,batch,nobs", [(11, 2, 3), (13, 1, 10), (17, 2, 2)])
+def test_diagonal_observables(dtype, n, batch, nobs):
+    """Expectations and adjoint gradients of Z-string sums (the diagonal
+    kernel: one tile at n = 11, one block at 13, many at 17; more than
+    eight observables leave the expectation on the general kernel and keep
+    the gradient seed on the diagonal one) against the oracle."""
+    rng = np.random.default_rng(500 + n)
+    ops = ("h", "rx", "ry", "rz", "cnot", "cz", "rzz")
+    c = W.random_circuit(rng, n, 3 * n, ops=ops)
+    params, data = W.random_params(rng, c, batch, per_sample=True)
+    obs = _diag_sums(rng, n, nobs, 5)
+    plan, st = gpu_forward(c, params, data, batch, dtype)
+    O = dq.Observable(n, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    tol = 1e-6 if dtype == "c64" else 1e-12
+    for b in range(batch):
+        want = oracle.state(c, params, data, b)
+        normwise(E[b], oracle.expvals(n, want, obs), RTOL[dtype], tol, "expval sample %d" % b)
+    w = rng.standard_normal((batch, nobs))
+    gp, _ = dq.adjoint_grad(plan, O, st, t64(params), t64(data), t64(w))
+    gp = gp.cpu().numpy()
+    src = [i for i, g in enumerate(c.gates) if g.src == "param"]
+    subset = src if n <= 13 else [src[k] for k in np.random.default_rng(5).choice(len(src), 6, replace=False)]
+    rp, _ = oracle.grad_param_shift(c, params, data, obs, w, batch, threads=8, gate_subset=subset)
+    idx = sorted(c.gates[i].idx for i in subset)
+    normwise(gp[:, idx], rp[:, idx], RTOL[dtype], tol, "d/dparams")
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_fold_init_matches_unfolded(dtype):
     rng = np.random.default_rng(7)

@@ -131,8 +131,7 @@ typedef struct {
                              complex128; with jit 5 and 4); 1..5 (complex128: 1..4) */
     int32_t low_bits;     /* states of 128 MiB and more: physical bits 3.. that every tile
                              includes, so that each wave reads runs of 2^(3+k) amplitudes:
-                             0 = auto (bits 3 and 4 in forward passes, bit 3 in adjoint
-                             passes), 1 = none, 2 = bit 3, 3 = bits 3 and 4 */
+                             0 = auto (bits 3 and 4), 1 = none, 2 = bit 3, 3 = bits 3 and 4 */
     int32_t layout;       /* 0 (default): for states of 128 MiB and more, try relabelling physical
                              bits 1..4 with wires spread over the register (transpositions,
                              undone by swaps appended to the circuit, so states keep the

@@ -236,11 +236,12 @@ struct Planner {
     uint64_t pinned = 0;
     explicit Planner(dq_plan_s &pl, bool adj, int r) : p(pl), adjoint(adj), R(r) {
         const int64_t state_bytes = (int64_t)(p.dbl ? 16 : 8) << p.n;
-        // auto: bits 3 and 4 for the forward; bit 3 only for the adjoint,
-        // whose passes carry twice the arithmetic per byte and gain more from
-        // one more free bit (more gates per pass) than they lose in access
-        // efficiency
-        const int want = p.opt.low_bits > 0 ? p.opt.low_bits - 1 : (adj ? 1 : 2);   // physical bits 3.. to pin
+        // auto: bits 3 and 4 in both directions.  Pinning bit 3 alone frees
+        // one more bit for gates (fewer adjoint passes), but its 128-byte
+        // pieces made the adjoint passes' speed depend on where the state's
+        // pages landed (27 to 37 ms per 32-qubit pass between runs of one
+        // plan, against 25 ms with 256-byte pieces)
+        const int want = p.opt.low_bits > 0 ? p.opt.low_bits - 1 : 2;   // physical bits 3.. to pin
         if (want > 0 && R >= 2 && p.n >= R + 8 && state_bytes >= (int64_t(128) << 20))
             pinned = want >= 2 ? (1ull << 3) | (1ull << 4) : (1ull << 3);
     }
@@ -411,6 +412,32 @@ struct Planner {
         prog.blk_hi = (int64_t)p.blocks.size();
     }
 
+    // A tile whose register bits all sit at byte offsets of 1 GiB or more,
+    // with lane bits other than 3, 4, 5, has each wave issue its loads to
+    // pieces of a few hundred bytes scattered over every 1 GiB region of the
+    // state: on MI355X such sweeps of two states ran at less than half the
+    // bandwidth of any other split of the same tile bits between lanes and
+    // registers.  Then the highest register bit becomes a lane bit, in place
+    // of the free lane bit with the most data-moving operations.
+    void far_register_rule(std::vector<int> &lanes, std::vector<int> &regs, const int *moves) const {
+        const int amp_log2 = p.dbl ? 4 : 3;
+        for (int b : regs)
+            if (b + amp_log2 < 30) return;
+        std::vector<int> sl(lanes);
+        std::sort(sl.begin(), sl.end());
+        if (sl[0] == 3 && sl[1] == 4 && sl[2] == 5) return;
+        int out = -1;   // lane to give up: never the pinned bit 3
+        for (int k = 0; k < 3; ++k) {
+            if (((pinned >> lanes[k]) & 1) != 0) continue;
+            if (out < 0 || moves[lanes[k]] > moves[lanes[out]] ||
+                (moves[lanes[k]] == moves[lanes[out]] && lanes[k] < lanes[out]))
+                out = k;
+        }
+        if (out < 0) return;
+        auto hi = std::max_element(regs.begin(), regs.end());
+        std::swap(lanes[out], *hi);
+    }
+
     void plan(Program &prog, std::vector<int> order, bool fuse_1q) {
         prog.slot_lo = (int64_t)p.slots.size();
         std::vector<int> rem = order;
@@ -484,6 +511,7 @@ struct Planner {
             for (int b = 0; b < 64; ++b) local[b] = -1;
             for (int b = 0; b < 3; ++b) local[b] = b;
             std::vector<int> lanes(freeb.begin(), freeb.begin() + 3), regs(freeb.begin() + 3, freeb.end());
+            far_register_rule(lanes, regs, moves);
             std::sort(lanes.begin(), lanes.end());
             std::sort(regs.begin(), regs.end());
             for (int k = 0; k < 3; ++k) {
@@ -1330,6 +1358,7 @@ dq_status dq_plan_describe(dq_plan plan, char *buf, size_t cap, size_t *needed) 
                          S.lbits[0], S.lbits[1], S.lbits[2]);
                 t += line;
                 for (int i = 0; i < S.R; ++i) t += std::to_string(S.rbits[i]) + (i + 1 < S.R ? "," : "");
+                if (k < prog.jk.size() && prog.jk[k] >= 0) t += " kernel=" + plan->jnames[(size_t)prog.jk[k]];
                 t += " ops=";
                 for (int64_t i = 0; i < S.nops; ++i) {
                     const TOp &o = plan->ops[(size_t)(S.op0 + i)];

@@ -64,14 +64,15 @@ def test_jit_hea_ring_family_equals_interpreted(n):
     chain): compiled and interpreted passes run the same operations in the
     same order, so expectations and gradients agree to float64 summation
     order; at n = 16 both also match the oracle.  At n = 25 the state (256
-    MiB) is large enough that every tile holds physical bits 3 and 4, and the
+    MiB) is large enough that every tile holds physical bits 3 (a lane bit) and
+    4 (a register bit), and the
     compiled plan uses the larger tiles (6 forward, 5 adjoint register bits)."""
     w = W.config(5, n=n, layers=6 if n < 25 else 3)
     obs = dq.Observable(n, w.observables)
     big = {"tile_bits": 6, "adj_tile_bits": 5} if n >= 25 else {}
     pj = dq.Plan(w.circuit, "c64", jit=True, **big)
     if n >= 25:
-        assert all(" lbits=3," in l for l in pj.describe().splitlines() if " tile " in l)
+        assert all(" lbits=3," in l and " rbits=4," in l for l in pj.describe().splitlines() if " tile " in l)
     Ej, gj = _step(pj, obs, w.params, n)
     Ei, gi = _step(dq.Plan(w.circuit, "c64", jit=False), obs, w.params, n)
     normwise(Ej, Ei, 1e-6, 1e-9, "expval jit vs interpreted")

@@ -4,42 +4,39 @@
 // bit positions, matrix slots relative to the pass) into the source of one
 // kernel: a straight-line sequence of calls into tile_dev.h whose operand
 // positions are template constants.  This file compiles such sources with
-// hipRTC for the current device's architecture, keeps the loaded kernels in
-// a process-wide cache keyed by a hash of (header, options, source), and
-// optionally stores the code objects on disk (DQ_JIT_CACHE, default
-// $HOME/.cache/dq_jit; "off" disables it).
+// hipRTC for the current device's architecture (jit_rtc.cpp), keeps the
+// loaded kernels in a process-wide cache keyed by a hash of (header,
+// options, source), and optionally stores the code objects on disk
+// (DQ_JIT_CACHE, default $HOME/.cache/dq_jit; "off" disables it).
+//
+// hipRTC serializes the compiles of one process, so a plan with several
+// passes to compile starts helper processes (dq_jitc, installed next to the
+// library), up to eight at a time, and compiles in-process whatever they did
+// not deliver.
 #include "dq_internal.h"
+#include "jit_rtc.h"
 
-#include <hip/hiprtc.h>
+#include <dlfcn.h>
+#include <spawn.h>
+#include <sys/stat.h>
+#include <sys/wait.h>
+#include <unistd.h>
 
-#include <atomic>
+#include <cerrno>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
-#include <sys/stat.h>
 #include <thread>
-#include <unistd.h>
 #include <vector>
 
-#include "tile_dev_src.inc"   // kTileDevSrc: the text of tile_dev.h (generated at build time)
+extern char **environ;
 
 namespace dq {
 namespace {
-
-const char *const kOpts[] = {"-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                             "-mllvm", "-simplifycfg-sink-common=false"};
-constexpr int kNOpts = sizeof(kOpts) / sizeof(kOpts[0]);
-
-uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull) {
-    for (unsigned char c : s) {
-        h ^= c;
-        h *= 1099511628211ull;
-    }
-    return h;
-}
 
 struct Entry {
     std::vector<char> code;
@@ -100,45 +97,79 @@ void write_file(const std::string &dir, const std::string &name, const std::vect
     else unlink(tmp.c_str());
 }
 
-// compile one kernel source; returns false with the compiler log in err
-bool compile(const std::string &src, const std::string &arch, std::vector<char> &code, std::string &err) {
-    hiprtcProgram prog;
-    const char *hdr = kTileDevSrc;
-    const char *hname = "tile_dev.h";
-    if (hiprtcCreateProgram(&prog, src.c_str(), "dq_pass.hip", 1, &hdr, &hname) != HIPRTC_SUCCESS) {
-        err = "hiprtcCreateProgram failed";
-        return false;
+// the helper program next to the shared library that holds this code, or ""
+std::string helper_path() {
+    Dl_info info;
+    if (!dladdr((void *)&helper_path, &info) || !info.dli_fname) return std::string();
+    const std::string lib(info.dli_fname);
+    const size_t k = lib.rfind('/');
+    const std::string p = (k == std::string::npos ? std::string(".") : lib.substr(0, k)) + "/dq_jitc";
+    return access(p.c_str(), X_OK) == 0 ? p : std::string();
+}
+
+bool write_all(const std::string &path, const std::string &text) {
+    FILE *f = fopen(path.c_str(), "wb");
+    if (!f) return false;
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+    return fclose(f) == 0 && ok;
+}
+
+// Compile srcs[i] in helper processes into codes[i] (left empty where a
+// helper could not be started or failed).  Each child only runs hipRTC.
+void compile_in_helpers(const std::vector<const std::string *> &srcs, const std::string &arch,
+                        std::vector<std::vector<char>> &codes) {
+    const std::string helper = helper_path();
+    if (helper.empty()) return;
+    const char *td = getenv("TMPDIR");
+    std::string tmpl = std::string(td && *td ? td : "/tmp") + "/dq_jit_XXXXXX";
+    std::vector<char> dbuf(tmpl.begin(), tmpl.end());
+    dbuf.push_back('\0');
+    if (!mkdtemp(dbuf.data())) return;
+    const std::string dir(dbuf.data());
+    const size_t n = srcs.size();
+    std::vector<std::string> in(n), out(n);
+    std::vector<char> written(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+        in[i] = dir + "/p" + std::to_string(i) + ".hip";
+        out[i] = dir + "/p" + std::to_string(i) + ".co";
+        written[i] = write_all(in[i], *srcs[i]) ? 1 : 0;
     }
-    std::vector<const char *> opts(kOpts, kOpts + kNOpts);
-    const std::string a = "--offload-arch=" + arch;
-    opts.push_back(a.c_str());
-    const hiprtcResult r = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
-    if (r != HIPRTC_SUCCESS) {
-        size_t n = 0;
-        hiprtcGetProgramLogSize(prog, &n);
-        std::string log(n, '\0');
-        if (n) hiprtcGetProgramLog(prog, &log[0]);
-        err = std::string("hipRTC: ") + hiprtcGetErrorString(r) + "\n" + log.substr(0, 4000);
-        hiprtcDestroyProgram(&prog);
-        return false;
+    unsigned par = std::thread::hardware_concurrency();
+    par = par < 1 ? 1 : (par > 8 ? 8 : par);
+    std::vector<std::pair<pid_t, size_t>> live;   // running helpers, oldest first
+    size_t next = 0;
+    while (next < n || !live.empty()) {
+        while (live.size() < par && next < n) {
+            const size_t i = next++;
+            if (!written[i]) continue;
+            std::vector<char *> argv = {const_cast<char *>(helper.c_str()), const_cast<char *>(arch.c_str()),
+                                        const_cast<char *>(in[i].c_str()), const_cast<char *>(out[i].c_str()), nullptr};
+            pid_t pid = 0;
+            if (posix_spawn(&pid, helper.c_str(), nullptr, nullptr, argv.data(), environ) == 0)
+                live.emplace_back(pid, i);
+        }
+        if (live.empty()) continue;
+        // wait for our own children only (never waitpid(-1): the process may
+        // have children of its own)
+        const pid_t pid = live.front().first;
+        const size_t i = live.front().second;
+        live.erase(live.begin());
+        int status = 0;
+        pid_t r;
+        do {
+            r = waitpid(pid, &status, 0);
+        } while (r < 0 && errno == EINTR);
+        if (r == pid && WIFEXITED(status) && WEXITSTATUS(status) == 0) read_file(out[i], codes[i]);
     }
-    size_t n = 0;
-    hiprtcGetCodeSize(prog, &n);
-    code.resize(n);
-    hiprtcGetCode(prog, code.data());
-    hiprtcDestroyProgram(&prog);
-    return true;
+    for (size_t i = 0; i < n; ++i) {
+        unlink(in[i].c_str());
+        unlink(out[i].c_str());
+    }
+    rmdir(dir.c_str());
 }
 
 }  // namespace
 
-std::string jit_key(const std::string &body) {
-    std::string salt(kTileDevSrc);
-    for (int i = 0; i < kNOpts; ++i) salt += kOpts[i];
-    char buf[32];
-    snprintf(buf, sizeof buf, "dqj_%016llx", (unsigned long long)fnv1a(body, fnv1a(salt)));
-    return buf;
-}
 
 bool jit_load(const std::vector<std::string> &names, const std::vector<std::string> &srcs,
               std::vector<hipFunction_t> &out, std::string &err) {
@@ -160,28 +191,31 @@ bool jit_load(const std::vector<std::string> &names, const std::vector<std::stri
         todo.push_back(i);
     }
     if (!todo.empty()) {
+        const auto t0 = std::chrono::steady_clock::now();
         std::vector<std::vector<char>> codes(todo.size());
-        std::vector<std::string> errs(todo.size());
-        std::vector<char> okv(todo.size(), 0);
-        std::atomic<size_t> next{0};
-        unsigned nt = std::thread::hardware_concurrency();
-        nt = nt < 1 ? 1 : (nt > 16 ? 16 : nt);
-        if (nt > todo.size()) nt = (unsigned)todo.size();
-        auto work = [&]() {
-            for (size_t j; (j = next++) < todo.size();)
-                okv[j] = compile(srcs[todo[j]], arch, codes[j], errs[j]) ? 1 : 0;
-        };
-        std::vector<std::thread> th;
-        for (unsigned t = 0; t < nt; ++t) th.emplace_back(work);
-        for (auto &t : th) t.join();
+        if (todo.size() > 1) {
+            std::vector<const std::string *> ts;
+            for (size_t j : todo) ts.push_back(&srcs[j]);
+            compile_in_helpers(ts, arch, codes);
+        }
+        size_t by_helpers = 0;
+        for (const auto &c : codes) by_helpers += c.empty() ? 0 : 1;
         for (size_t j = 0; j < todo.size(); ++j) {
-            if (!okv[j]) {
-                err = "compiling pass " + names[todo[j]] + ": " + errs[j];
-                return false;
+            if (codes[j].empty()) {
+                std::string e;
+                if (!jit_compile(srcs[todo[j]], arch, codes[j], e)) {
+                    err = "compiling pass " + names[todo[j]] + ": " + e;
+                    return false;
+                }
             }
             g_cache[names[todo[j]]].code = codes[j];
             write_file(dir, names[todo[j]] + "-" + arch + ".co", codes[j]);
         }
+        const char *vb = getenv("DQ_JIT_VERBOSE");
+        if (vb && *vb && strcmp(vb, "0") != 0)
+            fprintf(stderr, "dq jit: compiled %zu pass kernels for %s (%zu in helper processes, %zu in process) in %.1f s\n",
+                    todo.size(), arch.c_str(), by_helpers, todo.size() - by_helpers,
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     }
     out.assign(names.size(), nullptr);
     for (size_t i = 0; i < names.size(); ++i) {

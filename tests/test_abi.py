@@ -163,6 +163,33 @@ def test_jit_option_validation_and_sources(L):
     assert any("dq::gen_s<" in s for s in srcs)   # adjoint passes accumulate gradient terms
 
 
+def test_jit_helper_compiles_passes(L, tmp_path):
+    """The helper program beside the library (one hipRTC compile per process,
+    so that a plan's passes compile in parallel) turns a pass source into a
+    gfx950 code object holding that kernel, and reports a broken source with
+    a non-zero status and the compiler's message."""
+    import subprocess
+    import paper_2512_18995_amd as dq
+    from workloads import config
+    helper = os.path.join(os.path.dirname(L.LIB_PATH), "dq_jitc")
+    assert os.access(helper, os.X_OK)
+    w = config(5, n=12, layers=2)
+    src = dq.Plan(w.circuit, "c64", jit=True).jit_sources()[-1]
+    (tmp_path / "p.hip").write_text(src)
+    r = subprocess.run([helper, "gfx950", str(tmp_path / "p.hip"), str(tmp_path / "p.co")], capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    code = (tmp_path / "p.co").read_bytes()
+    assert code[:4] == b"\x7fELF"
+    name = re.search(r"void (dqj_[0-9a-f]{16})\(", src).group(1)
+    assert name.encode() in code
+    (tmp_path / "bad.hip").write_text(src.replace("dq::jit_", "dq::no_such_"))
+    r = subprocess.run([helper, "gfx950", str(tmp_path / "bad.hip"), str(tmp_path / "bad.co")], capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 1 and "no_such_" in r.stderr
+    assert not (tmp_path / "bad.co").exists()
+
+
 @pytest.mark.skipif(not os.path.exists("/opt/rocm/lib/libhiprtc.so"), reason="hipRTC not installed")
 def test_jit_source_compiles_for_gfx950(L):
     """The generated pass kernels compile with hipRTC against tile_dev.h for

@@ -223,6 +223,11 @@ int64_t add_slot(dq_plan_s &p, int dim, const std::vector<int> &factors, int dag
 }
 
 // ---------------------------------------------------------------- planner
+// operations x amplitudes per lane (per state) of the longest pass that is
+// compiled; a 32-qubit HEA pass (about 23 operations on 64 amplitudes per
+// lane) compiles in about 10 s, an 84-operation one in about a minute
+constexpr int64_t kJitMaxWork = 2048;
+
 struct Planner {
     dq_plan_s &p;
     bool adjoint;
@@ -234,7 +239,13 @@ struct Planner {
     // bandwidth the memory system sustains once the state no longer fits the
     // last-level cache.
     uint64_t pinned = 0;
+    // operations per pass in compiled plans: a longer pass would exceed the
+    // compiled-kernel size limit and run interpreted, and the interpreted
+    // kernel with 64 registers per lane keeps its tile in scratch memory
+    int max_ops = 0;        // 0: no limit
+    bool fusing = false;    // one-qubit gates on a wire fold into one operation (forward)
     explicit Planner(dq_plan_s &pl, bool adj, int r) : p(pl), adjoint(adj), R(r) {
+        if (p.opt.jit && R > 0) max_ops = (int)(kJitMaxWork >> R);
         const int64_t state_bytes = (int64_t)(p.dbl ? 16 : 8) << p.n;
         // auto: bits 3 and 4 in both directions.  Pinning bit 3 alone frees
         // one more bit for gates (fewer adjoint passes), but its 128-byte
@@ -268,6 +279,8 @@ struct Planner {
         uint64_t blocked = 0;
         std::vector<int> out;
         int lslots = 0;
+        int ops = 0;                // operations after folding (an estimate: folds up to SLOT_MAXF)
+        uint64_t last_1q = 0;       // bits whose last selected gate is a one-qubit gate
         auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
         if (seed >= 0) {
             int q[5], nq;
@@ -289,9 +302,14 @@ struct Planner {
                 blocked |= Q;
                 continue;
             }
+            const bool folds = fusing && nq == 1 && ((last_1q >> q[0]) & 1);
+            if (max_ops && !folds && ops >= max_ops) break;
             S |= need;
             out.push_back((int)r);
             if (diff(g)) ++lslots;
+            if (!folds) ++ops;
+            if (nq == 1) last_1q |= 1ull << q[0];
+            else last_1q &= ~Q;
         }
         return out;
     }
@@ -439,6 +457,7 @@ struct Planner {
     }
 
     void plan(Program &prog, std::vector<int> order, bool fuse_1q) {
+        fusing = fuse_1q;
         prog.slot_lo = (int64_t)p.slots.size();
         std::vector<int> rem = order;
         while (!rem.empty()) {
@@ -841,10 +860,6 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
     return b;
 }
 
-// operations x amplitudes per lane (per state) of the longest pass that is
-// compiled; a 32-qubit HEA pass (about 23 operations on 64 amplitudes per
-// lane) compiles in about 10 s, an 84-operation one in about a minute
-constexpr int64_t kJitMaxWork = 2048;
 
 void jit_generate(dq_plan_s &p) {
     std::map<std::string, int> index;

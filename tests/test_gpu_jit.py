@@ -119,3 +119,17 @@ def test_jit_graph_replay():
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(E, E0) and torch.equal(G, G0)
+
+
+def test_jit_qft_is_dft():
+    """The compiled passes of the QFT (Hadamards, controlled phases, the
+    wire-reversing swaps) applied to a random 17-qubit state equal the
+    unitary inverse DFT of that state."""
+    from gpu_helpers import rand_state
+    n = 17
+    rng = np.random.default_rng(517)
+    x = rand_state(rng, n)
+    c = W.qft(n)
+    plan, st = gpu_forward(c, None, None, 1, "c64", True, init=x, jit=True)
+    assert len(plan.jit_sources()) > 0
+    assert_state(st.cpu().numpy()[0], np.fft.ifft(x, norm="ortho"), "c64", len(c.gates), "QFT")

@@ -114,7 +114,8 @@ typedef struct {
     int32_t fusion;       /* 1 (default): register-tile passes that apply many gates per
                              state sweep; 0: the plain path, one kernel launch per gate */
     int32_t tile_bits;    /* register-resident wires per tile: 0 = auto (5 for complex64,
-                             4 for complex128; with jit 6 and 5); 1..6 (complex128: 1..5) */
+                             4 for complex128; with jit 6 and 5); 1..6 (complex128: 1..5;
+                             6 only with jit, else 5 is used) */
     int32_t fold_init;    /* 1 (default): fold the leading one-qubit gates of every wire into
                              the initial product-state write when applying from |0..0> */
     int32_t dense_fuse;   /* 0 (default): register tiles; 4 or 5: the forward sweep groups gates
@@ -124,8 +125,9 @@ typedef struct {
                              time; 1: each distinct pass is compiled (hipRTC, at the plan's first
                              use on a device; code objects cached in DQ_JIT_CACHE, default
                              $HOME/.cache/dq_jit) into straight-line code with every operand
-                             position a compile-time constant; passes longer than 2048
-                             operations x amplitudes per lane stay interpreted */
+                             position a compile-time constant; the planner keeps passes
+                             within 2048 operations x amplitudes per lane (a longer pass
+                             with up to 32 amplitudes per lane would stay interpreted) */
     int32_t adj_tile_bits; /* register-resident wires per tile of the adjoint sweep, which holds
                              two states: 0 = auto (min(tile bits, 4) for complex64, 3 for
                              complex128; with jit 5 and 4); 1..5 (complex128: 1..4) */

@@ -279,8 +279,9 @@ struct Planner {
         uint64_t blocked = 0;
         std::vector<int> out;
         int lslots = 0;
-        int ops = 0;                // operations after folding (an estimate: folds up to SLOT_MAXF)
+        int ops = 0;                // operations after folding, as plan() will fold
         uint64_t last_1q = 0;       // bits whose last selected gate is a one-qubit gate
+        int scount[64];             // per bit: gates folded into its current one-qubit slot
         auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
         if (seed >= 0) {
             int q[5], nq;
@@ -302,14 +303,18 @@ struct Planner {
                 blocked |= Q;
                 continue;
             }
-            const bool folds = fusing && nq == 1 && ((last_1q >> q[0]) & 1);
+            const bool folds = fusing && nq == 1 && ((last_1q >> q[0]) & 1) && scount[q[0]] < SLOT_MAXF;
             if (max_ops && !folds && ops >= max_ops) break;
             S |= need;
             out.push_back((int)r);
             if (diff(g)) ++lslots;
             if (!folds) ++ops;
-            if (nq == 1) last_1q |= 1ull << q[0];
-            else last_1q &= ~Q;
+            if (nq == 1) {
+                scount[q[0]] = folds ? scount[q[0]] + 1 : 1;
+                last_1q |= 1ull << q[0];
+            } else {
+                last_1q &= ~Q;
+            }
         }
         return out;
     }
@@ -456,6 +461,8 @@ struct Planner {
         std::swap(lanes[out], *hi);
     }
 
+    static bool real1(int op) { return op == OP_RY || op == OP_H || op == OP_X || op == OP_Z; }
+
     void plan(Program &prog, std::vector<int> order, bool fuse_1q) {
         fusing = fuse_1q;
         prog.slot_lo = (int64_t)p.slots.size();
@@ -601,7 +608,7 @@ struct Planner {
                 for (int f = 0; f < sl.nf; ++f) {
                     const int op = p.gates[sl.f[f]].op;
                     diag = diag && is_diag1(op);
-                    real = real && (op == OP_RY || op == OP_H || op == OP_X || op == OP_Z);
+                    real = real && real1(op);
                 }
                 if (diag) o.kind = TK_1QDIAG;
                 else if (real) o.kind = TK_1QREAL;
@@ -641,7 +648,9 @@ int default_R(const dq_plan_s &p) {
     // need no registers for dispatch, hold twice that
     const int base = p.opt.jit ? (p.dbl ? 5 : 6) : (p.dbl ? 4 : 5);
     int R = p.opt.tile_bits > 0 ? p.opt.tile_bits : base;
-    if (p.dbl && R > 5) R = 5;
+    // 64 amplitudes per lane only in compiled passes: the interpreted kernel
+    // cannot keep that many in registers (its tile went to scratch memory)
+    if ((p.dbl || !p.opt.jit) && R > 5) R = 5;
     if (R > p.n - 6) R = p.n - 6;
     return R < 0 ? 0 : R;
 }
@@ -870,8 +879,10 @@ void jit_generate(dq_plan_s &p) {
             const Step &S = prog.steps[k];
             if (S.kind != ST_TILE) continue;
             // compile time grows faster than linearly with the length of the
-            // straight-line code: longer passes stay interpreted
-            if (S.nops * (int64_t(1) << S.R) > kJitMaxWork) continue;
+            // straight-line code: longer passes stay interpreted, except
+            // 64-amplitude tiles, which have no interpreted kernel (the
+            // planner keeps them within the limit in any case)
+            if (S.R < 6 && S.nops * (int64_t(1) << S.R) > kJitMaxWork) continue;
             int64_t s0 = 0;
             const std::string body = pass_body(p, S, adj, s0);
             auto it = index.find(body);

@@ -110,6 +110,22 @@ template <typename T> using cx = cpx<T>;
 using C64 = cpx<float>;
 using C128 = cpx<double>;
 
+// Streaming accesses of tile passes: every amplitude is read once and written
+// once per pass, so loads and stores carry the non-temporal hint (the state
+// does not stay in the caches between passes in any case).
+template <typename T> __device__ __forceinline__ cpx<T> ld_stream(const cpx<T> *p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 x = __builtin_nontemporal_load((const v2 *)p);
+    return cpx<T>{x.x, x.y};
+}
+template <typename T> __device__ __forceinline__ void st_stream(cpx<T> *p, cpx<T> a) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 x;
+    x.x = a.x;
+    x.y = a.y;
+    __builtin_nontemporal_store(x, (v2 *)p);
+}
+
 __device__ __forceinline__ float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -693,7 +709,7 @@ __device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, co
     V v[1][NR];
     {
         V *tp = st + base;
-        DQ_SF(NR, { v[0][i] = (tp + reg_off<R>(i, rbits))[lo]; });
+        DQ_SF(NR, { v[0][i] = ld_stream(tp + reg_off<R>(i, rbits) + lo); });
     }
     body(v);
     // recompute the addresses for the stores rather than keeping the loads'
@@ -701,7 +717,7 @@ __device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, co
     asm volatile("" : "+s"(base));
     {
         V *tp = st + base;
-        DQ_SF(NR, { (tp + reg_off<R>(i, rbits))[lo] = v[0][i]; });
+        DQ_SF(NR, { st_stream(tp + reg_off<R>(i, rbits) + lo, v[0][i]); });
     }
 }
 
@@ -727,8 +743,8 @@ __device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, i
             V *pp = st + sbase + base;
             V *qp = lam + lbase + base;
             DQ_SF(NR, {
-                v[0][i] = (pp + reg_off<R>(i, rbits))[lo];
-                v[1][i] = (qp + reg_off<R>(i, rbits))[lo];
+                v[0][i] = ld_stream(pp + reg_off<R>(i, rbits) + lo);
+                v[1][i] = ld_stream(qp + reg_off<R>(i, rbits) + lo);
             });
         }
         body(v, acc);
@@ -737,8 +753,8 @@ __device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, i
             V *pp = st + sbase + base;
             V *qp = lam + lbase + base;
             DQ_SF(NR, {
-                (pp + reg_off<R>(i, rbits))[lo] = v[0][i];
-                (qp + reg_off<R>(i, rbits))[lo] = v[1][i];
+                st_stream(pp + reg_off<R>(i, rbits) + lo, v[0][i]);
+                st_stream(qp + reg_off<R>(i, rbits) + lo, v[1][i]);
             });
         }
     }

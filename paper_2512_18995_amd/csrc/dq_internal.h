@@ -61,6 +61,7 @@ struct MultiEntry {
     const TOp *ops;
     const int32_t *lsg;
     int32_t n, nops, nls, wps, ngrad;
+    int32_t nt;                // 1: non-temporal loads and stores (see TileArgs)
     int32_t rbits[MAX_TILE_R];
     int32_t lbits[3];
     int32_t tbits[MAX_TILE_R + 3];

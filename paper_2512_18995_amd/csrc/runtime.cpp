@@ -227,6 +227,9 @@ int64_t add_slot(dq_plan_s &p, int dim, const std::vector<int> &factors, int dag
 // compiled; a 32-qubit HEA pass (about 23 operations on 64 amplitudes per
 // lane) compiles in about 10 s, an 84-operation one in about a minute
 constexpr int64_t kJitMaxWork = 2048;
+// working sets beyond the 256 MB last-level cache are swept with
+// non-temporal loads and stores (smaller ones keep their cache reuse)
+constexpr double kStreamBytes = 256.0 * 1024 * 1024;
 
 struct Planner {
     dq_plan_s &p;
@@ -777,6 +780,8 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
     if (s0 < 0) s0 = 0;
     const char *T = p.dbl ? "double" : "float";
     const int R = S.R, NR = 1 << R, NS = adj ? 2 : 1;
+    // compiled per plan: the streaming choice follows one sample's working set
+    const char *nt = std::ldexp((double)NS * (p.dbl ? 16 : 8), p.n) > kStreamBytes ? "true" : "false";
     // occupancy target (waves per SIMD): two while a lane holds up to 64
     // complex64 amplitudes of one state (32 of each of two in the adjoint)
     const int rb = NR * (p.dbl ? 8 : 4);
@@ -788,9 +793,9 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
     if (adj) {
         snprintf(line, sizeof line,
                  "    extern __shared__ double acc[];\n"
-                 "    dq::jit_adj<%s, %d>(a, acc, [&](auto &v, auto m, int lane, double *ac) {\n", T, R);
+                 "    dq::jit_adj<%s, %d, %s>(a, acc, [&](auto &v, auto m, int lane, double *ac) {\n", T, R, nt);
     } else {
-        snprintf(line, sizeof line, "    dq::jit_fwd<%s, %d>(a, [&](auto &v, auto m, int lane) {\n", T, R);
+        snprintf(line, sizeof line, "    dq::jit_fwd<%s, %d, %s>(a, [&](auto &v, auto m, int lane) {\n", T, R, nt);
     }
     b += line;
     const TOp *ops = p.ops.data() + S.op0;
@@ -1168,6 +1173,7 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
             a.lslot_gslot = d.lsg + S.ls0;
             a.wps = wps;
             a.ngrad = p.ngrad;
+            a.nt = std::ldexp((double)batch * (lam ? 2 : 1) * (p.dbl ? 16 : 8), p.n) > kStreamBytes ? 1 : 0;
             const size_t si = (size_t)(&S - prog.steps.data());
             if (!prog.jk.empty() && prog.jk[si] >= 0 && (size_t)prog.jk[si] < d.jfn.size()) {
                 a.mats = (const char *)mats + prog.js0[si] * (p.dbl ? 16 : 8);
@@ -1828,6 +1834,7 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
                              tile_only(p->adj, m->R_adj));
     }
     // depth tables
+    const double tot_bytes = (double)m->st_total * (double)amp;   // all circuits' states
     for (int pass = 0; pass < 2; ++pass) {
         auto &tab = pass ? m->adj : m->fwd;
         auto &tabc = pass ? m->adj_c : m->fwd_c;
@@ -1850,6 +1857,7 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
                 E.lam_off = (int64_t)(m->ws_off[c] + L.lam);
                 E.part_off = (int64_t)(m->ws_off[c] + L.part);
                 E.ngrad = p->ngrad;
+                E.nt = tot_bytes * (pass ? 2 : 1) > kStreamBytes ? 1 : 0;
                 const int64_t tiles = int64_t(1) << (p->n - 6 - (pass ? m->R_adj : m->R_fwd));
                 E.wps = (int32_t)(pass ? grad_waves(*p, 1) : 1);
                 E.unit_begin = units[d];

@@ -58,6 +58,8 @@ struct TileArgs {
     double *partial;           // adjoint: [B][wps][ngrad]
     const int32_t *lslot_gslot;// adjoint: global gradient index of each local slot
     int32_t wps, ngrad;
+    int32_t nt;                // 1: loads and stores with the non-temporal hint
+    int32_t pad_;
 };
 
 
@@ -111,8 +113,9 @@ using C64 = cpx<float>;
 using C128 = cpx<double>;
 
 // Streaming accesses of tile passes: every amplitude is read once and written
-// once per pass, so loads and stores carry the non-temporal hint (the state
-// does not stay in the caches between passes in any case).
+// once per pass, so when the working set exceeds the last-level cache the
+// loads and stores carry the non-temporal hint (a smaller state would stay in
+// that cache between passes, and the hint costs it that reuse).
 template <typename T> __device__ __forceinline__ cpx<T> ld_stream(const cpx<T> *p) {
     typedef T v2 __attribute__((ext_vector_type(2)));
     const v2 x = __builtin_nontemporal_load((const v2 *)p);
@@ -703,13 +706,18 @@ template <typename T, int R> constexpr int adj_waves() { return (1 << R) * sizeo
 // One forward tile: load 2^R amplitudes per lane, run the operations
 // (body(v): an op-list interpreter, or a pass compiled at plan time), store.
 template <typename T, int R, typename Body>
-__device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, const int32_t *rbits, Body &&body) {
+__device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, const int32_t *rbits, bool nt,
+                                         Body &&body) {
     using V = cx<T>;
     constexpr int NR = 1 << R;
     V v[1][NR];
     {
         V *tp = st + base;
-        DQ_SF(NR, { v[0][i] = ld_stream(tp + reg_off<R>(i, rbits) + lo); });
+        if (nt) {
+            DQ_SF(NR, { v[0][i] = ld_stream(tp + reg_off<R>(i, rbits) + lo); });
+        } else {
+            DQ_SF(NR, { v[0][i] = (tp + reg_off<R>(i, rbits))[lo]; });
+        }
     }
     body(v);
     // recompute the addresses for the stores rather than keeping the loads'
@@ -717,7 +725,11 @@ __device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, co
     asm volatile("" : "+s"(base));
     {
         V *tp = st + base;
-        DQ_SF(NR, { st_stream(tp + reg_off<R>(i, rbits) + lo, v[0][i]); });
+        if (nt) {
+            DQ_SF(NR, { st_stream(tp + reg_off<R>(i, rbits) + lo, v[0][i]); });
+        } else {
+            DQ_SF(NR, { (tp + reg_off<R>(i, rbits))[lo] = v[0][i]; });
+        }
     }
 }
 
@@ -730,7 +742,7 @@ template <typename T, int R, typename Body>
 __device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, int64_t lbase, int n,
                                          const int32_t *rbits, const int32_t *lbits, const int32_t *tbits, int nls,
                                          int64_t w, int64_t wps, double *partial_row, const int32_t *lslot_gslot,
-                                         double *acc, int lane, Body &&body) {
+                                         double *acc, int lane, bool nt, Body &&body) {
     using V = cx<T>;
     constexpr int NR = 1 << R;
     const int64_t tps = int64_t(1) << (n - 6 - R);
@@ -742,20 +754,34 @@ __device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, i
         {
             V *pp = st + sbase + base;
             V *qp = lam + lbase + base;
-            DQ_SF(NR, {
-                v[0][i] = ld_stream(pp + reg_off<R>(i, rbits) + lo);
-                v[1][i] = ld_stream(qp + reg_off<R>(i, rbits) + lo);
-            });
+            if (nt) {
+                DQ_SF(NR, {
+                    v[0][i] = ld_stream(pp + reg_off<R>(i, rbits) + lo);
+                    v[1][i] = ld_stream(qp + reg_off<R>(i, rbits) + lo);
+                });
+            } else {
+                DQ_SF(NR, {
+                    v[0][i] = (pp + reg_off<R>(i, rbits))[lo];
+                    v[1][i] = (qp + reg_off<R>(i, rbits))[lo];
+                });
+            }
         }
         body(v, acc);
         asm volatile("" : "+s"(base));
         {
             V *pp = st + sbase + base;
             V *qp = lam + lbase + base;
-            DQ_SF(NR, {
-                st_stream(pp + reg_off<R>(i, rbits) + lo, v[0][i]);
-                st_stream(qp + reg_off<R>(i, rbits) + lo, v[1][i]);
-            });
+            if (nt) {
+                DQ_SF(NR, {
+                    st_stream(pp + reg_off<R>(i, rbits) + lo, v[0][i]);
+                    st_stream(qp + reg_off<R>(i, rbits) + lo, v[1][i]);
+                });
+            } else {
+                DQ_SF(NR, {
+                    (pp + reg_off<R>(i, rbits))[lo] = v[0][i];
+                    (qp + reg_off<R>(i, rbits))[lo] = v[1][i];
+                });
+            }
         }
     }
     for (int s = 0; s < nls; ++s) {
@@ -968,7 +994,7 @@ __device__ __forceinline__ T gen_s(const cx<T> (&v)[NR], const cx<T> (&l)[NR], i
 // sample in a grid-stride loop; the adjoint runs work unit blockIdx.x of
 // sample blockIdx.y (as the interpreted passes do).  a.mats points at the
 // pass's first matrix.
-template <typename T, int R, typename Body>
+template <typename T, int R, bool NT, typename Body>
 __device__ __forceinline__ void jit_fwd(const TileArgs &a, Body &&body) {
     using V = cx<T>;
     const int lane = threadIdx.x;
@@ -980,18 +1006,18 @@ __device__ __forceinline__ void jit_fwd(const TileArgs &a, Body &&body) {
         const int64_t b = tile >> tshift;
         const int64_t base = (b << a.n) + tile_base<R>(tile & tmask, a.tbits);
         const cptr<V> m = to_const((const V *)a.mats + b * a.mstride);
-        fwd_tile<T, R>((V *)a.st, base, lo, a.rbits, [&](V (&v)[1][1 << R]) { body(v, m, lane); });
+        fwd_tile<T, R>((V *)a.st, base, lo, a.rbits, NT, [&](V (&v)[1][1 << R]) { body(v, m, lane); });
     }
 }
 
-template <typename T, int R, typename Body>
+template <typename T, int R, bool NT, typename Body>
 __device__ __forceinline__ void jit_adj(const TileArgs &a, double *acc, Body &&body) {
     using V = cx<T>;
     const int64_t b = blockIdx.y;
     const int lane = threadIdx.x;
     const cptr<V> m = to_const((const V *)a.mats + b * a.mstride);
     adj_unit<T, R>((V *)a.st, (V *)a.lam, b << a.n, b << a.n, a.n, a.rbits, a.lbits, a.tbits, a.nlslots, blockIdx.x,
-                   a.wps, a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, lane,
+                   a.wps, a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, lane, NT,
                    [&](V (&v)[2][1 << R], double *ac) { body(v, m, lane, ac); });
 }
 

@@ -35,6 +35,7 @@ __device__ __forceinline__ MultiEntry ld_entry(cptr<MultiEntry> ents, int e) {
     E.nls = ents[e].nls;
     E.wps = ents[e].wps;
     E.ngrad = ents[e].ngrad;
+    E.nt = ents[e].nt;
     for (int k = 0; k < MAX_TILE_R; ++k) E.rbits[k] = ents[e].rbits[k];
     for (int k = 0; k < 3; ++k) E.lbits[k] = ents[e].lbits[k];
     for (int k = 0; k < MAX_TILE_R + 3; ++k) E.tbits[k] = ents[e].tbits[k];
@@ -44,8 +45,8 @@ __device__ __forceinline__ MultiEntry ld_entry(cptr<MultiEntry> ents, int e) {
 // Interpreted passes: the op list is read from memory and dispatched per op.
 template <typename T, int R>
 __device__ __forceinline__ void fwd_tile_ops(cx<T> *st, int64_t base, int64_t lo, const int32_t *rbits, cptr<TOp> ops,
-                                             int nops, cptr<cx<T>> m, int lane) {
-    fwd_tile<T, R>(st, base, lo, rbits, [&](cx<T> (&v)[1][1 << R]) {
+                                             int nops, cptr<cx<T>> m, int lane, bool nt) {
+    fwd_tile<T, R>(st, base, lo, rbits, nt, [&](cx<T> (&v)[1][1 << R]) {
         for (int k = 0; k < nops; ++k) apply_op<T, 1, 1 << R>(v, ld_op(ops, k), m, lane);
     });
 }
@@ -54,9 +55,10 @@ template <typename T, int R>
 __device__ __forceinline__ void adj_unit_ops(cx<T> *st, cx<T> *lam, int64_t sbase, int64_t lbase, int n,
                                              const int32_t *rbits, const int32_t *lbits, const int32_t *tbits,
                                              cptr<TOp> ops, int nops, int nls, cptr<cx<T>> m, int64_t w, int64_t wps,
-                                             double *partial_row, const int32_t *lslot_gslot, double *acc, int lane) {
+                                             double *partial_row, const int32_t *lslot_gslot, double *acc, int lane,
+                                             bool nt) {
     constexpr int NR = 1 << R;
-    adj_unit<T, R>(st, lam, sbase, lbase, n, rbits, lbits, tbits, nls, w, wps, partial_row, lslot_gslot, acc, lane,
+    adj_unit<T, R>(st, lam, sbase, lbase, n, rbits, lbits, tbits, nls, w, wps, partial_row, lslot_gslot, acc, lane, nt,
                    [&](cx<T> (&v)[2][NR], double *ac) {
                        for (int k = 0; k < nops; ++k) {
                            const TOp op = ld_op(ops, k);
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(64, (tile_waves<T, R>())) void k_tile_fwd(TileArgs 
         const int64_t b = tile >> tshift;
         const int64_t base = (b << a.n) + tile_base<R>(tile & tmask, a.tbits);   // wave-uniform
         fwd_tile_ops<T, R>((V *)a.st, base, lo, a.rbits, to_const(a.ops), a.nops,
-                           to_const((const V *)a.mats + b * a.mstride), lane);
+                           to_const((const V *)a.mats + b * a.mstride), lane, a.nt != 0);
     }
 }
 
@@ -89,7 +91,8 @@ __global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj(TileArgs a
     const int64_t b = blockIdx.y;
     adj_unit_ops<T, R>((V *)a.st, (V *)a.lam, b << a.n, b << a.n, a.n, a.rbits, a.lbits, a.tbits, to_const(a.ops),
                        a.nops, a.nlslots, to_const((const V *)a.mats + b * a.mstride), blockIdx.x, a.wps,
-                       a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, threadIdx.x);
+                       a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, threadIdx.x,
+                       a.nt != 0);
 }
 
 // ---------------------------------------------------------------- uneven batches
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(64, (tile_waves<T, R>())) void k_tile_fwd_multi(cx<
         const MultiEntry E = ld_entry(ents, e);
         const int64_t base = E.st_off + tile_base<R>(u - E.unit_begin, E.tbits);
         fwd_tile_ops<T, R>(st, base, lane_off(lane, E.lbits), E.rbits, to_const(E.ops), E.nops,
-                           to_const((const V *)(ws + E.mats_off)), lane);
+                           to_const((const V *)(ws + E.mats_off)), lane, E.nt != 0);
     }
 }
 
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(64, (adj_waves<T, R>())) void k_tile_adj_multi(cx<T
     const int64_t w = u - E.unit_begin;
     adj_unit_ops<T, R>(st, (V *)(ws + E.lam_off), E.st_off, 0, E.n, E.rbits, E.lbits, E.tbits, to_const(E.ops),
                        E.nops, E.nls, to_const((const V *)(ws + E.mats_off)), w, E.wps,
-                       (double *)(ws + E.part_off) + w * (int64_t)E.ngrad, E.lsg, acc, threadIdx.x);
+                       (double *)(ws + E.part_off) + w * (int64_t)E.ngrad, E.lsg, acc, threadIdx.x, E.nt != 0);
 }
 
 

@@ -222,6 +222,32 @@ dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const doubl
 dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, double *out,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* Marginal probabilities of a computational-basis measurement of the wires
+ * wires[0..nwires) (paper 4.2: measurement of a circuit with its
+ * probabilities; 4.1: the Born rule): out[b][m] = sum of |psi_b[j]|^2 over
+ * the basis states j whose measured wires read m, wires[0] being the most
+ * significant bit of m.  nwires 1..12 distinct wires below n; batch at most
+ * 65535; out: device [batch][2^nwires] float64; ws: caller-owned device
+ * buffer of at least dq_probs_workspace_size(plan, batch, nwires) bytes.
+ * One read of the state; deterministic (fixed-order float64 sums).  Invalid
+ * arguments are rejected on the host before any device work
+ * (DQ_ERR_INVALID_ARG, DQ_ERR_WORKSPACE, DQ_ERR_OUT_OF_RANGE). */
+dq_status dq_probs_workspace_size(dq_plan plan, int64_t batch, int32_t nwires, size_t *bytes);
+dq_status dq_probs(dq_plan plan, const void *state, int64_t batch, const int32_t *wires, int32_t nwires,
+                   double *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Measurement shots by inversion of the cumulative distribution (paper
+ * 4.2: sampling a circuit's measurement): out[b][s] = the smallest outcome m
+ * with u[b][s] < p[b][0] + ... + p[b][m] (summed in this order in float64),
+ * or the last outcome of nonzero probability when u[b][s] is not below the
+ * total (rounding); 0 when every probability is 0.  p: device
+ * [batch][nout] float64 (dq_probs's output, or any distribution), nout
+ * 1..2^20; u: device [batch][shots] float64 uniforms in [0, 1) drawn by the
+ * caller; out: device [batch][shots] int64.  No workspace; host validation
+ * as above. */
+dq_status dq_sample(const double *p, int64_t batch, int32_t nout, const double *u, int32_t shots, int64_t *out,
+                    void *stream);
+
 /* Adjoint gradient (paper 7.2) of L = sum_{b,o} grad_out[b][o] E[b][o]
  * where E is dq_expval of the final state.  `state` must hold the final
  * states produced by dq_apply_circuit with the same params / data; it is

@@ -176,6 +176,40 @@ def prob_zero(n: int, psi: np.ndarray, wire: int) -> float:
     return lib().orc_prob_zero(n, _dp(pv), wire)
 
 
+def probs(n: int, psi: np.ndarray, wires: Sequence[int]) -> np.ndarray:
+    """Marginal probabilities of a computational-basis measurement of
+    ``wires`` (measurement of section 4.2; the Born rule behind the state
+    evolution of section 4.1): P[m] = sum of |psi_j|^2 over the basis states
+    j whose measured wires read m, wires[0] being the most significant bit
+    of m and wire w being bit n-1-w of j."""
+    j = np.arange(1 << n, dtype=np.int64)
+    m = np.zeros(1 << n, dtype=np.int64)
+    for w in wires:
+        m = (m << 1) | ((j >> (n - 1 - w)) & 1)
+    out = np.zeros(1 << len(wires))
+    np.add.at(out, m, np.abs(np.asarray(psi, dtype=np.complex128)) ** 2)
+    return out
+
+
+def sample(p: Sequence[float], u: Sequence[float]) -> np.ndarray:
+    """Shots by inverse transform (sampling of section 4.2's measurement):
+    for each uniform x the smallest outcome m with x < p[0] + ... + p[m]
+    (summed in this order), else the last outcome of nonzero probability
+    (x not below the total), else 0 (no probability at all)."""
+    out = []
+    for x in u:
+        c, last, res = 0.0, -1, -1
+        for m, pm in enumerate(p):
+            if pm > 0:
+                last = m
+            c += pm
+            if x < c:
+                res = m
+                break
+        out.append(res if res >= 0 else (last if last >= 0 else 0))
+    return np.array(out, dtype=np.int64)
+
+
 def _pool(threads: Optional[int]):
     return ThreadPoolExecutor(max_workers=threads or 1)
 

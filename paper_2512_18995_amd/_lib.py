@@ -25,7 +25,7 @@ EXPORTS = ["dq_plan_create", "dq_plan_destroy", "dq_plan_get_stats", "dq_obs_cre
            "dq_last_error", "dq_version", "dq_profile_enable", "dq_profile_read",
            "dq_multi_create", "dq_multi_destroy", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
            "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe",
-           "dq_plan_jit_source"]
+           "dq_plan_jit_source", "dq_probs_workspace_size", "dq_probs", "dq_sample"]
 PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other", "dense"]
 
 
@@ -99,12 +99,16 @@ def lib():
         L.dq_multi_apply.argtypes = [vp, vp, vp, vp, c_size_t, vp]
         L.dq_multi_expval.argtypes = [vp, vp, vp, vp, c_size_t, vp]
         L.dq_multi_adjoint_grad.argtypes = [vp, vp, vp, vp, vp, vp, c_size_t, vp]
+        L.dq_probs_workspace_size.argtypes = [vp, c_int64, c_int32, POINTER(c_size_t)]
+        L.dq_probs.argtypes = [vp, vp, c_int64, POINTER(c_int32), c_int32, vp, vp, c_size_t, vp]
+        L.dq_sample.argtypes = [vp, c_int64, c_int32, vp, c_int32, vp, vp]
         L.dq_last_error.restype = c_char_p
         L.dq_version.restype = c_int32
         for f in ("dq_plan_create", "dq_plan_get_stats", "dq_obs_create", "dq_workspace_size", "dq_state_init",
                   "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read",
                   "dq_multi_create", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
-                  "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe", "dq_plan_jit_source"):
+                  "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe", "dq_plan_jit_source",
+                  "dq_probs_workspace_size", "dq_probs", "dq_sample"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib

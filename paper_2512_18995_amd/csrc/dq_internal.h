@@ -165,6 +165,20 @@ inline int zdiag_blocks(int n) {
 }
 // expectations; terms dt0..dt1 (group 0, X-free) go through the diagonal
 // kernel into dpart ([batch][blocks][nobs] doubles) when dt0 < dt1
+// marginal probabilities (kernels.hip): measured wires' physical bits in
+// wire order (pb) and ascending (asc)
+constexpr int PROB_MAXW = 12;
+struct ProbArgs {
+    int32_t n, k;
+    int32_t pb[PROB_MAXW];
+    int32_t asc[PROB_MAXW];
+};
+// amplitudes one block of k_probs_part sums (256 threads x 16)
+constexpr int64_t PROB_CHUNK = 4096;
+hipError_t launch_probs(int dbl, const void *st, int64_t batch, const ProbArgs &a, double *partial, int64_t bpo,
+                        double *out, hipStream_t s);
+hipError_t launch_sample(const double *p, int64_t batch, int32_t nout, const double *u, int32_t shots, int64_t *out,
+                         hipStream_t s);
 hipError_t launch_expval(int dbl, const void *st, int32_t n, int64_t batch, const DGroup *groups, int32_t ngroups,
                          const DTerm *terms, int32_t nterms, int32_t nobs, double *partial, int32_t eb, double *out,
                          int32_t dt0, int32_t dt1, double *dpart, hipStream_t s);

@@ -793,6 +793,74 @@ __global__ __launch_bounds__(256) void k_lambda(const cx<T> *psi, cx<T> *lam, in
 }  // namespace
 
 // ============================================================ launchers
+// ============================================================ measurement
+// Marginal probabilities.  Block (x, o, b) sums |psi_b[j]|^2 over chunk x of
+// the basis states whose measured bits read o: j is the chunk index r with
+// zeros inserted at the measured physical bits (ascending) and o's bits set
+// there, so consecutive threads read consecutive amplitudes whenever the
+// measured bits lie above the low ones.  One partial per block, summed in a
+// fixed order by k_probs_final.
+template <typename T>
+__global__ __launch_bounds__(256) void k_probs_part(const cx<T> *psi, ProbArgs a, int64_t per_outcome,
+                                                    double *partial, int64_t bpo) {
+    __shared__ double red[4];
+    const int64_t o = blockIdx.y, b = blockIdx.z;
+    const int K = 1 << a.k;
+    uint64_t set = 0;
+    for (int i = 0; i < a.k; ++i)
+        if ((o >> (a.k - 1 - i)) & 1) set |= 1ull << a.pb[i];
+    const cx<T> *p = psi + (b << a.n);
+    double acc = 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * PROB_CHUNK + threadIdx.x;
+#pragma unroll 4
+    for (int t = 0; t < (int)(PROB_CHUNK / 256); ++t) {
+        const int64_t r = r0 + t * 256;
+        if (r < per_outcome) {
+            int64_t j = r;
+            for (int i = 0; i < a.k; ++i) j = insert_zero(j, a.asc[i]);
+            const cx<T> v = p[(uint64_t)j | set];
+            acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(b * K + o) * bpo + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[row] = sum of the row's bpo partials (row = b * 2^k + o), fixed order
+__global__ __launch_bounds__(256) void k_probs_final(const double *partial, int64_t bpo, double *out) {
+    __shared__ double red[4];
+    const int64_t row = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < bpo; i += 256) acc += partial[row * bpo + i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[row] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One shot per thread: the first outcome whose running sum exceeds u.
+__global__ __launch_bounds__(256) void k_sample(const double *p, int64_t batch, int nout, const double *u, int shots,
+                                                int64_t *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= batch * shots) return;
+    const double *q = p + (i / shots) * nout;
+    const double x = u[i];
+    double c = 0.0;
+    int64_t last = -1, res = -1;
+    for (int m = 0; m < nout; ++m) {
+        const double pm = q[m];
+        if (pm > 0.0) last = m;
+        c += pm;
+        if (x < c) {
+            res = m;
+            break;
+        }
+    }
+    out[i] = res >= 0 ? res : (last >= 0 ? last : 0);
+}
+
 #define DQ_LAUNCH_RET return hipGetLastError()
 
 hipError_t launch_prepare(int dbl, const DGate *gates, const void *fixed, const DSlot *slots, int32_t nslots,
@@ -998,6 +1066,29 @@ hipError_t launch_grad_final(const double *partial, int64_t batch, int32_t wps, 
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, partial, batch, wps, ngrad,
                        csr_off, csr_g, csr_f, nout, per_sample, out);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_probs(int dbl, const void *st, int64_t batch, const ProbArgs &a, double *partial, int64_t bpo,
+                        double *out, hipStream_t s) {
+    const int64_t per_outcome = int64_t(1) << (a.n - a.k);
+    dim3 g((unsigned)bpo, (unsigned)(1u << a.k), (unsigned)batch);
+    if (dbl)
+        hipLaunchKernelGGL(k_probs_part<double>, g, dim3(256), 0, s, (const C128 *)st, a, per_outcome, partial, bpo);
+    else
+        hipLaunchKernelGGL(k_probs_part<float>, g, dim3(256), 0, s, (const C64 *)st, a, per_outcome, partial, bpo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probs_final, dim3((unsigned)(batch << a.k)), dim3(256), 0, s, (const double *)partial, bpo,
+                       out);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_sample(const double *p, int64_t batch, int32_t nout, const double *u, int32_t shots, int64_t *out,
+                         hipStream_t s) {
+    const int64_t total = batch * shots;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, p, batch, nout, u, shots,
+                       out);
     DQ_LAUNCH_RET;
 }
 

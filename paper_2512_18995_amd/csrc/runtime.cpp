@@ -1586,6 +1586,65 @@ dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, 
     return ok();
 }
 
+namespace {
+// blocks per outcome of the probability reduction
+int64_t probs_blocks(const dq_plan_s &p, int32_t nwires) {
+    const int64_t per = int64_t(1) << (p.n - nwires);
+    return (per + PROB_CHUNK - 1) / PROB_CHUNK;
+}
+}  // namespace
+
+dq_status dq_probs_workspace_size(dq_plan plan, int64_t batch, int32_t nwires, size_t *bytes) {
+    if (!plan || !bytes) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    dq_status st = check_batch(*plan, batch);
+    if (st != DQ_OK) return st;
+    if (nwires < 1 || nwires > PROB_MAXW || nwires > plan->n)
+        return fail(DQ_ERR_INVALID_ARG, "nwires %d outside 1..%d", nwires, std::min(PROB_MAXW, (int)plan->n));
+    *bytes = align256((size_t)batch * ((size_t)1 << nwires) * (size_t)probs_blocks(*plan, nwires) * sizeof(double));
+    return ok();
+}
+
+dq_status dq_probs(dq_plan plan, const void *state, int64_t batch, const int32_t *wires, int32_t nwires, double *out,
+                   void *ws, size_t ws_bytes, void *stream) {
+    if (!plan || !state || !wires || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    size_t need = 0;
+    dq_status st = dq_probs_workspace_size(plan, batch, nwires, &need);
+    if (st != DQ_OK) return st;
+    ProbArgs a{};
+    a.n = plan->n;
+    a.k = nwires;
+    uint64_t seen = 0;
+    for (int i = 0; i < nwires; ++i) {
+        if (wires[i] < 0 || wires[i] >= plan->n)
+            return fail(DQ_ERR_INVALID_ARG, "wire %d outside 0..%d", wires[i], plan->n - 1);
+        if ((seen >> wires[i]) & 1) return fail(DQ_ERR_INVALID_ARG, "wire %d listed twice", wires[i]);
+        seen |= 1ull << wires[i];
+        a.pb[i] = plan->n - 1 - wires[i];   // wire w -> physical bit n-1-w
+        a.asc[i] = a.pb[i];
+    }
+    std::sort(a.asc, a.asc + nwires);
+    if (!ws || ws_bytes < need)
+        return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+    ProfScope pr(*plan, DQ_PROF_OTHER, 2, state_bytes(*plan, batch), (hipStream_t)stream);
+    const hipError_t e = launch_probs(plan->dbl, state, batch, a, (double *)ws, probs_blocks(*plan, nwires), out,
+                                      (hipStream_t)stream);
+    pr.done();
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "probs: %s", hipGetErrorString(e));
+    return ok();
+}
+
+dq_status dq_sample(const double *p, int64_t batch, int32_t nout, const double *u, int32_t shots, int64_t *out,
+                    void *stream) {
+    if (!p || !u || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (batch < 1 || batch > 65535) return fail(DQ_ERR_OUT_OF_RANGE, "batch %lld outside 1..65535", (long long)batch);
+    if (nout < 1 || nout > (1 << 20)) return fail(DQ_ERR_INVALID_ARG, "nout %d outside 1..2^20", nout);
+    if (shots < 0) return fail(DQ_ERR_INVALID_ARG, "shots %d is negative", shots);
+    if (shots == 0) return ok();
+    const hipError_t e = launch_sample(p, batch, nout, u, shots, out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "sample: %s", hipGetErrorString(e));
+    return ok();
+}
+
 dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, const double *params,
                           int64_t params_bstride, const double *data, int64_t data_bstride, const double *grad_out,
                           double *grad_params, double *grad_data, int32_t preserve_state, void *ws, size_t ws_bytes,

@@ -199,6 +199,38 @@ def expval(plan: Plan, obs: Observable, state: torch.Tensor, ws: Optional[torch.
     return out
 
 
+def probs(plan: Plan, state: torch.Tensor, wires, ws: Optional[torch.Tensor] = None,
+          out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Marginal probabilities [B, 2^k] of measuring ``wires`` (k <= 12; the
+    first listed wire is the most significant bit of the outcome index)."""
+    _check_state(plan, state)
+    dev = state.device
+    B = state.shape[0]
+    w = (ctypes.c_int32 * len(wires))(*[int(x) for x in wires])
+    if out is None:
+        out = torch.empty((B, 1 << len(wires)), dtype=torch.float64, device=dev)
+    if ws is None:
+        n = ctypes.c_size_t(0)
+        check(lib().dq_probs_workspace_size(plan.handle, B, len(wires), ctypes.byref(n)), "dq_probs_workspace_size")
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+    check(lib().dq_probs(plan.handle, state.data_ptr(), B, w, len(wires), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                         _stream(dev)), "dq_probs")
+    return out
+
+
+def sample(p: torch.Tensor, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Outcomes [B, shots] (int64) of the distributions p [B, nout] (float64)
+    for the caller's uniforms u [B, shots] in [0, 1): inverse transform."""
+    if p.dtype != torch.float64 or u.dtype != torch.float64 or p.dim() != 2 or u.dim() != 2 or \
+            p.shape[0] != u.shape[0] or not p.is_contiguous() or not u.is_contiguous() or p.device != u.device:
+        raise ValueError("p [B, nout] and u [B, shots]: contiguous float64 on one device")
+    if out is None:
+        out = torch.empty(u.shape, dtype=torch.int64, device=u.device)
+    check(lib().dq_sample(p.data_ptr(), p.shape[0], p.shape[1], u.data_ptr(), u.shape[1], out.data_ptr(),
+                          _stream(u.device)), "dq_sample")
+    return out
+
+
 def adjoint_grad(plan: Plan, obs: Observable, state: torch.Tensor, params, data, grad_out: torch.Tensor,
                  preserve_state: bool = False, ws: Optional[torch.Tensor] = None, want_data: bool = True):
     """VJP of sum_{b,o} grad_out[b,o] E[b,o] w.r.t. params and data (adjoint

@@ -233,4 +233,51 @@ def pin_marginal_probability():
         _close(oracle.prob_zero(n, psi, w), np.cos(t[w] / 2) ** 2, 1e-14, "P(w=%d)" % w)
 
 
+def pin_marginal_distribution():
+    """Marginals of several wires (first listed wire = most significant bit
+    of the outcome): on a product of RY(t_w)|0> states the Kronecker product
+    of the per-wire [cos^2(t/2), sin^2(t/2)] in the listed order; on
+    (|0..0> + |1..1>)/sqrt(2) half on all-zero and half on all-one; over all
+    wires in order |psi|^2 itself and in reverse order its bit reversal; a
+    single wire agrees with the C routine's P(w = 0)."""
+    rng = np.random.default_rng(11)
+    n = 5
+    t = rng.uniform(0, 2 * np.pi, n)
+    c = W.Circuit(n, [W.Gate("ry", (q,), "param", q) for q in range(n)], n)
+    psi = oracle.state(c, t)
+    for wires in ([3, 0, 4], [0], [4, 1], [2, 3, 1, 0]):
+        want = np.ones(1)
+        for w in wires:
+            want = np.kron(want, [np.cos(t[w] / 2) ** 2, np.sin(t[w] / 2) ** 2])
+        _close(oracle.probs(n, psi, wires), want, 1e-14, "product-state marginal %s" % wires)
+    ghz = np.zeros(1 << n, complex)
+    ghz[0] = ghz[-1] = 1 / np.sqrt(2)
+    _close(oracle.probs(n, ghz, [2, 0]), [0.5, 0, 0, 0.5], 1e-15, "GHZ two-wire marginal")
+    x = _rand_state(rng, n)
+    _close(oracle.probs(n, x, list(range(n))), np.abs(x) ** 2, 1e-15, "all wires")
+    rev = np.array([int(format(j, "0%db" % n)[::-1], 2) for j in range(1 << n)])
+    _close(oracle.probs(n, x, list(range(n))[::-1]), (np.abs(x) ** 2)[rev], 1e-15, "all wires reversed")
+    for w in range(n):
+        p0 = oracle.prob_zero(n, x, w)
+        _close(oracle.probs(n, x, [w]), [p0, 1 - p0], 1e-14, "single wire %d vs the C routine" % w)
+
+
+def pin_sampling():
+    """Inverse transform on a hand-made distribution at and around its
+    cumulative sums (a uniform equal to a cumulative sum belongs to the next
+    outcome; zero-probability outcomes are never drawn; a uniform not below
+    the total gives the last outcome of nonzero probability), and the
+    frequencies of 200000 seeded uniforms within 5 standard deviations."""
+    p = [0.2, 0.0, 0.5, 0.3, 0.0]
+    u = [0.0, 0.1999999, 0.2, 0.6999999, 0.7, 0.9999999, 1.0, 1.5]
+    assert list(oracle.sample(p, u)) == [0, 0, 2, 2, 3, 3, 3, 3], list(oracle.sample(p, u))
+    assert list(oracle.sample([0.0, 0.0], [0.3])) == [0]
+    rng = np.random.default_rng(12)
+    q = rng.dirichlet(np.ones(6))
+    N = 200000
+    counts = np.bincount(oracle.sample(q, rng.uniform(0, 1, N)), minlength=6)
+    sd = np.sqrt(N * q * (1 - q))
+    assert np.all(np.abs(counts - N * q) <= 5 * sd + 1), (counts, N * q)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

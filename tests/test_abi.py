@@ -145,6 +145,50 @@ def test_calls_validate_before_device_work(L):
     lib.dq_plan_destroy(h)
 
 
+def test_probs_and_sample_validate_before_device_work(L):
+    """Marginal probabilities and sampling reject bad arguments on the host
+    with the documented codes, and report the workspace the reduction needs
+    (one float64 partial per block of 4096 amplitudes per outcome)."""
+    n = 14
+    st, h = _create(L, n, [G("h", (q,)) for q in range(n)])
+    assert st == 0
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced
+    size = ctypes.c_size_t()
+    for B, k in ((1, 1), (3, 4), (2, 12)):
+        assert lib.dq_probs_workspace_size(h, B, k, ctypes.byref(size)) == 0
+        blocks = -(-(1 << (n - k)) // 4096)
+        assert size.value == -(-(B * (1 << k) * blocks * 8) // 256) * 256, (B, k, size.value)
+    assert lib.dq_probs_workspace_size(h, 1, 0, ctypes.byref(size)) == 1
+    assert lib.dq_probs_workspace_size(h, 1, 13, ctypes.byref(size)) == 1
+    assert lib.dq_probs_workspace_size(h, 0, 2, ctypes.byref(size)) == 1
+    assert lib.dq_probs_workspace_size(h, 70000, 2, ctypes.byref(size)) == 4
+
+    def probs(wires, B=1, ws=1 << 30, state=fake, out=fake):
+        w = (ctypes.c_int32 * max(len(wires), 1))(*wires)
+        return lib.dq_probs(h, state, B, w, len(wires), out, fake, ws, None)
+    assert probs([0, n]) == 1                    # wire beyond the register
+    assert probs([-1]) == 1
+    assert probs([3, 5, 3]) == 1                 # repeated wire
+    assert "twice" in lib.dq_last_error().decode()
+    assert probs([]) == 1
+    assert probs(list(range(13))) == 1           # more than 12 wires
+    assert probs([1, 2], state=None) == 1
+    assert probs([1, 2], out=None) == 1
+    assert probs([1, 2], ws=64) == 3             # workspace too small
+    assert "workspace" in lib.dq_last_error().decode()
+    # sampling
+    assert lib.dq_sample(None, 1, 4, fake, 8, fake, None) == 1
+    assert lib.dq_sample(fake, 1, 4, None, 8, fake, None) == 1
+    assert lib.dq_sample(fake, 1, 4, fake, 8, None, None) == 1
+    assert lib.dq_sample(fake, 1, 0, fake, 8, fake, None) == 1
+    assert lib.dq_sample(fake, 1, (1 << 20) + 1, fake, 8, fake, None) == 1
+    assert lib.dq_sample(fake, 1, 4, fake, -1, fake, None) == 1
+    assert lib.dq_sample(fake, 0, 4, fake, 8, fake, None) == 4
+    assert lib.dq_sample(fake, 1, 4, fake, 0, fake, None) == 0    # no shots: nothing to do
+    lib.dq_plan_destroy(h)
+
+
 def test_jit_option_validation_and_sources(L):
     """jit must be 0 or 1; a jit plan lists one kernel per distinct tile pass,
     and passes that repeat (equal operation lists) share a kernel."""

@@ -453,3 +453,60 @@ def test_layout_search_keeps_canonical_order(jit):
     assert_state(out["auto"][0], out["canonical"][0].astype(np.complex128), "c64", 2 * len(w.circuit.gates), "state")
     normwise(out["auto"][1], out["canonical"][1], RTOL["c64"], 1e-7, "expval")
     normwise(out["auto"][2], out["canonical"][2], RTOL["c64"], 1e-7, "gradient")
+
+
+# ------------------------------------------------------------------ measurement
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,batch", [(5, 2), (9, 3), (13, 2)])
+def test_marginal_probabilities_and_sampling(dtype, n, batch):
+    """Marginals of several wire lists (the top wire, the bottom wire, mixed
+    order, a random set, every wire when n <= 12) against the oracle on
+    random circuit states; shots drawn from the device marginals for seeded
+    uniforms, some equal to a cumulative sum (the boundary case) or above
+    the total, against the oracle's inverse transform of the same float64
+    marginals (an integer decision on identical inputs: bit-exact)."""
+    rng = np.random.default_rng(700 + n)
+    c = W.random_circuit(rng, n, 6 * n, with_data=True, max_unitary_k=min(3, n))
+    params, data = W.random_params(rng, c, batch, per_sample=True)
+    plan, st = gpu_forward(c, params, data, batch, dtype)
+    lists = [[0], [n - 1], [n - 1, 0, n // 2], [int(w) for w in rng.choice(n, min(4, n), replace=False)]]
+    if n <= 12:
+        lists.append(list(range(n)))
+    states = [oracle.state(c, params, data, b) for b in range(batch)]
+    for wires in lists:
+        P = dq.probs(plan, st, wires)
+        Pn = P.cpu().numpy()
+        for b in range(batch):
+            want = oracle.probs(n, states[b], wires)
+            normwise(Pn[b], want, RTOL[dtype], 1e-7 if dtype == "c64" else 1e-14, "marginal %s, sample %d" % (wires, b))
+        shots = 300
+        u = rng.uniform(0, 1, (batch, shots))
+        cs = np.cumsum(Pn, axis=1)
+        k = min(shots - 1, Pn.shape[1])
+        u[:, :k] = cs[:, :k]                     # exactly on the cumulative sums
+        u[:, -1] = 1.0                           # not below the total
+        got = dq.sample(P, torch.as_tensor(u, device=DEV)).cpu().numpy()
+        for b in range(batch):
+            want = oracle.sample(Pn[b], u[b])
+            assert np.array_equal(got[b], want), ("shots", wires, b, np.flatnonzero(got[b] != want)[:5])
+
+
+def test_marginals_of_a_large_product_state():
+    """26 qubits (a 512 MiB complex64 state, beyond the last-level cache):
+    after RY(t_w) on every wire the marginal of wires [25, 0, 13] is the
+    Kronecker product of [cos^2(t/2), sin^2(t/2)] in that order, and the
+    marginal of one wire sums to 1."""
+    n = 26
+    rng = np.random.default_rng(26)
+    t = rng.uniform(0, 2 * np.pi, n)
+    c = W.Circuit(n, [W.Gate("ry", (q,), "param", q) for q in range(n)], n)
+    plan, st = gpu_forward(c, t, None, 1, "c64")
+    wires = [25, 0, 13]
+    want = np.ones(1)
+    for w in wires:
+        want = np.kron(want, [np.cos(t[w] / 2) ** 2, np.sin(t[w] / 2) ** 2])
+    P = dq.probs(plan, st, wires).cpu().numpy()[0]
+    normwise(P, want, 1e-5, 1e-7, "product-state marginal at 26 qubits")
+    assert abs(dq.probs(plan, st, [7]).cpu().numpy()[0].sum() - 1.0) < 1e-5
+    del st
+    torch.cuda.empty_cache()

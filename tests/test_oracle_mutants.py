@@ -80,3 +80,31 @@ for pin in oracle_pins.ALL_PINS:
     except Exception as e:
         print("CAUGHT", pin.__name__, str(e)[:100].replace(chr(10), " "))
 """
+
+
+# Planted mistakes in the numpy part of the oracle (marginals and sampling):
+# (name, function, exact text in its source, replacement, pins that must fail)
+PY_MUTANTS = [
+    ("probs-lsb-wire0", "probs", "((j >> (n - 1 - w)) & 1)", "((j >> w) & 1)", ["pin_marginal_distribution"]),
+    ("probs-order-reversed", "probs", "for w in wires:", "for w in list(wires)[::-1]:",
+     ["pin_marginal_distribution"]),
+    ("probs-amplitude-not-squared", "probs", "np.abs(np.asarray(psi, dtype=np.complex128)) ** 2",
+     "np.abs(np.asarray(psi, dtype=np.complex128))", ["pin_marginal_distribution"]),
+    ("sample-le", "sample", "if x < c:", "if x <= c:", ["pin_sampling"]),
+    ("sample-no-fallback", "sample", "out.append(res if res >= 0 else (last if last >= 0 else 0))",
+     "out.append(res if res >= 0 else 0)", ["pin_sampling"]),
+]
+
+
+@pytest.mark.parametrize("name,func,old,new,pins", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_python_mutant_is_caught(monkeypatch, name, func, old, new, pins):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(getattr(oracle, func)))
+    assert src.count(old) == 1, "mutant %s: anchor text not found once" % name
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), "<mutant %s>" % name, "exec"), ns)
+    monkeypatch.setattr(oracle, func, ns[func])
+    for pin in pins:
+        with pytest.raises(AssertionError):
+            getattr(oracle_pins, pin)()

@@ -159,6 +159,7 @@ struct dq_plan_s {
     bool has_fold = false;
     std::vector<std::string> jnames, jsrcs;   // compiled passes: kernel names and sources
     int64_t user_gates = 0;                    // gates given by the caller (the layout may append swaps)
+    int64_t entry_gates = 0;                   // last gates of the list: run first, by the forward from a given state only
     int32_t layout_swaps = 0;
     std::vector<int64_t> fold_off;      // per physical bit: slot offset of the folded column, -1 none
     int64_t folded_gates = 0;
@@ -659,7 +660,8 @@ int default_R(const dq_plan_s &p) {
 }
 
 dq_status build_plan(dq_plan_s &p) {
-    const int G = (int)p.gates.size();
+    const int G_all = (int)p.gates.size();
+    const int G = G_all - (int)p.entry_gates;   // the circuit proper; entry gates follow it in the list
     const bool fused = p.opt.fusion != 0;
     p.R_fwd = fused ? default_R(p) : 0;
     // two states per tile in the adjoint: fewer register bits by default
@@ -668,7 +670,7 @@ dq_status build_plan(dq_plan_s &p) {
     if (ra > p.n - 6) ra = p.n - 6;
     p.R_adj = fused && ra > 0 ? ra : 0;
     // gradient slots: every differentiable gate occurrence, in gate order
-    std::vector<int> gslot(G, -1);
+    std::vector<int> gslot(G_all, -1);
     p.ngrad = 0;
     for (int g = 0; g < G; ++g)
         if (p.gates[g].src != SRC_NONE && is_rotation(p.gates[g].op)) gslot[g] = p.ngrad++;
@@ -696,12 +698,15 @@ dq_status build_plan(dq_plan_s &p) {
     for (int g = 0; g < G; ++g) order[g] = g;
     const int dense_k = fused ? p.opt.dense_fuse : 0;
     const bool dense = dense_k >= 4 && p.n >= dense_k + (p.dbl ? 4 : 5);
-    // forward, all gates
+    // forward from a given state: the entry gates, then the circuit
     {
+        std::vector<int> full;
+        for (int g = G; g < G_all; ++g) full.push_back(g);
+        full.insert(full.end(), order.begin(), order.end());
         Planner pl(p, false, p.R_fwd);
         pl.gslot_of = gslot;
-        if (dense) pl.plan_dense(p.fwd_full, order, dense_k);
-        else pl.plan(p.fwd_full, order, true);
+        if (dense) pl.plan_dense(p.fwd_full, full, dense_k);
+        else pl.plan(p.fwd_full, full, true);
     }
     // forward from |0..0> with the leading one-qubit gates of every wire folded
     p.fold_off.assign(p.n, -1);
@@ -932,6 +937,7 @@ dq_plan_s *plan_clone_base(const dq_plan_s &p) {
     q->ndata = p.ndata;
     q->fixed = p.fixed;
     q->user_gates = p.user_gates;
+    q->entry_gates = 0;
     return q;
 }
 
@@ -964,15 +970,21 @@ dq_plan_s *search_layout(dq_plan_s *p) {
             q->gates = base;
             for (DGate &g : q->gates)
                 for (int i = 0; i < g.nq; ++i) g.bits[i] = perm[g.bits[i]];
-            for (int j = 0; j < k; ++j) {   // back to the canonical order at the end
-                DGate sw{};
-                sw.op = OP_SWAP;
-                sw.nq = 2;
-                sw.bits[0] = tgt[k - 1 - j];
-                sw.bits[1] = lows[j];
-                sw.src = SRC_NONE;
-                q->gates.push_back(sw);
-            }
+            // back to the canonical order at the end; and, for a forward from a
+            // given state (not |0..0>, which the relabelling leaves alone),
+            // into the relabelled order at the start: the same transpositions,
+            // kept at the end of the list as entry gates
+            for (int rep = 0; rep < 2; ++rep)
+                for (int j = 0; j < k; ++j) {
+                    DGate sw{};
+                    sw.op = OP_SWAP;
+                    sw.nq = 2;
+                    sw.bits[0] = tgt[k - 1 - j];
+                    sw.bits[1] = lows[j];
+                    sw.src = SRC_NONE;
+                    q->gates.push_back(sw);
+                }
+            q->entry_gates = k;
             q->layout_swaps = k;
             if (build_plan(*q) == DQ_OK && plan_cost(*q) < best) {
                 best = plan_cost(*q);

@@ -510,3 +510,34 @@ def test_marginals_of_a_large_product_state():
     assert abs(dq.probs(plan, st, [7]).cpu().numpy()[0].sum() - 1.0) < 1e-5
     del st
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("jit", [True, False], ids=["compiled", "interpreted"])
+def test_large_states_against_references(jit):
+    """24 qubits (a 128 MiB complex64 state: low physical bits pinned into
+    every tile, qubit layout searched): the QFT of a random state (applied
+    to a given state, so the relabelled layout must be entered first) equals
+    numpy's inverse DFT, and two HEA layers from |0..0> equal the oracle's
+    state; in both cases with the searched layout and the canonical one."""
+    n = 24
+    rng = np.random.default_rng(24)
+    x = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    x /= np.linalg.norm(x)
+    want = np.fft.ifft(x, norm="ortho")
+    c = W.qft(n)
+    w = W.config(5, n=n, layers=2)
+    ref = oracle.state(w.circuit, w.params)
+    for layout in ("auto", "canonical"):
+        plan = dq.Plan(c, "c64", jit=jit, layout=layout)
+        assert (plan.stats()["layout_swaps"] > 0) == (layout == "auto")
+        st = plan.state(1, DEV)
+        dq.state_init(plan, st, torch.as_tensor(x.astype(np.complex64), device=DEV))
+        dq.apply_circuit(plan, st, None, None, from_zero=False)
+        assert_state(st.cpu().numpy()[0], want, "c64", len(c.gates), "QFT, layout %s" % layout)
+        del st
+        plan = dq.Plan(w.circuit, "c64", jit=jit, layout=layout)
+        st = plan.state(1, DEV)
+        dq.apply_circuit(plan, st, t64(w.params), None, from_zero=True)
+        assert_state(st.cpu().numpy()[0], ref, "c64", len(w.circuit.gates), "HEA, layout %s" % layout)
+        del st
+        torch.cuda.empty_cache()

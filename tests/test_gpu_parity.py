@@ -518,7 +518,8 @@ def test_large_states_against_references(jit):
     every tile, qubit layout searched): the QFT of a random state (applied
     to a given state, so the relabelled layout must be entered first) equals
     numpy's inverse DFT, and two HEA layers from |0..0> equal the oracle's
-    state; in both cases with the searched layout and the canonical one."""
+    state and give its ZZ-chain expectation (the diagonal-observable kernel);
+    in both cases with the searched layout and the canonical one."""
     n = 24
     rng = np.random.default_rng(24)
     x = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
@@ -527,6 +528,7 @@ def test_large_states_against_references(jit):
     c = W.qft(n)
     w = W.config(5, n=n, layers=2)
     ref = oracle.state(w.circuit, w.params)
+    e_ref = oracle.expvals(n, ref, w.observables)
     for layout in ("auto", "canonical"):
         plan = dq.Plan(c, "c64", jit=jit, layout=layout)
         assert (plan.stats()["layout_swaps"] > 0) == (layout == "auto")
@@ -539,5 +541,7 @@ def test_large_states_against_references(jit):
         st = plan.state(1, DEV)
         dq.apply_circuit(plan, st, t64(w.params), None, from_zero=True)
         assert_state(st.cpu().numpy()[0], ref, "c64", len(w.circuit.gates), "HEA, layout %s" % layout)
+        E = dq.expval(plan, dq.Observable(n, w.observables), st).cpu().numpy()[0]
+        normwise(E, e_ref, RTOL["c64"], 1e-7, "ZZ-chain expectation, layout %s" % layout)
         del st
         torch.cuda.empty_cache()

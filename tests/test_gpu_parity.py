@@ -518,8 +518,10 @@ def test_large_states_against_references(jit):
     every tile, qubit layout searched): the QFT of a random state (applied
     to a given state, so the relabelled layout must be entered first) equals
     numpy's inverse DFT, and two HEA layers from |0..0> equal the oracle's
-    state and give its ZZ-chain expectation (the diagonal-observable kernel);
-    in both cases with the searched layout and the canonical one."""
+    state, give its ZZ-chain expectation (the diagonal-observable kernel) and
+    the adjoint gradient of two of its parameters (parameter shift on
+    the oracle); in both cases with the searched layout and the canonical
+    one."""
     n = 24
     rng = np.random.default_rng(24)
     x = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
@@ -529,6 +531,12 @@ def test_large_states_against_references(jit):
     w = W.config(5, n=n, layers=2)
     ref = oracle.state(w.circuit, w.params)
     e_ref = oracle.expvals(n, ref, w.observables)
+    # parameter shift on the oracle for two parameters
+    pick = [0, 2 * n + n // 2]                # an RY of the first and of the second layer
+    gates = [i for i, gt in enumerate(w.circuit.gates) if gt.src == "param" and gt.idx in pick]
+    rp, _ = oracle.grad_param_shift(w.circuit, w.params, None, w.observables, np.ones((1, 1)), 1, threads=8,
+                                    gate_subset=gates)
+    g_ref = [float(np.asarray(rp).reshape(-1)[k]) for k in pick]
     for layout in ("auto", "canonical"):
         plan = dq.Plan(c, "c64", jit=jit, layout=layout)
         assert (plan.stats()["layout_swaps"] > 0) == (layout == "auto")
@@ -541,7 +549,15 @@ def test_large_states_against_references(jit):
         st = plan.state(1, DEV)
         dq.apply_circuit(plan, st, t64(w.params), None, from_zero=True)
         assert_state(st.cpu().numpy()[0], ref, "c64", len(w.circuit.gates), "HEA, layout %s" % layout)
-        E = dq.expval(plan, dq.Observable(n, w.observables), st).cpu().numpy()[0]
+        O = dq.Observable(n, w.observables)
+        E = dq.expval(plan, O, st).cpu().numpy()[0]
         normwise(E, e_ref, RTOL["c64"], 1e-7, "ZZ-chain expectation, layout %s" % layout)
+        g, _ = dq.adjoint_grad(plan, O, st, t64(w.params), None, t64(np.ones((1, 1))))
+        g = g.cpu().numpy()
+        # complex64 gradient entries are sums over 2^24 amplitudes that cancel
+        # far below |<lambda|psi>|: compared on the scale of the observable
+        scale = sum(abs(cf) for cf, _ in w.observables[0])
+        for k, r in zip(pick, g_ref):
+            assert abs(g[k] - r) <= 1e-5 * scale, ("d/dtheta_%d, layout %s" % (k, layout), g[k], r)
         del st
         torch.cuda.empty_cache()

@@ -82,7 +82,9 @@ typedef enum {
     DQ_OP_RX = 4, DQ_OP_RY = 5, DQ_OP_RZ = 6,
     DQ_OP_CNOT = 7, DQ_OP_CZ = 8, DQ_OP_SWAP = 9,
     DQ_OP_CP = 10, DQ_OP_RZZ = 11,
-    DQ_OP_UNITARY = 12          /* dense 2^nq x 2^nq matrix, nq = 1..5 */
+    DQ_OP_UNITARY = 12,         /* dense 2^nq x 2^nq matrix, nq = 1..5 */
+    DQ_OP_RXX = 13,             /* exp(-i t X(x)X / 2) and exp(-i t Y(x)Y / 2): the two-qubit */
+    DQ_OP_RYY = 14              /* rotations of the paper's gate set beside RZZ (section 4) */
 } dq_op;
 
 typedef enum { DQ_SRC_NONE = 0, DQ_SRC_PARAM = 1, DQ_SRC_DATA = 2 } dq_src;

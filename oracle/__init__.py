@@ -37,9 +37,9 @@ _SRC = os.path.join(_HERE, "dq_oracle.c")
 _SO = os.path.join(_HERE, "_dq_oracle.so")
 
 OPCODE = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "cnot": 7, "cz": 8,
-          "swap": 9, "cp": 10, "rzz": 11, "unitary": 12}
+          "swap": 9, "cp": 10, "rzz": 11, "unitary": 12, "rxx": 13, "ryy": 14}
 # gates whose derivative the two-term shift rule gives exactly
-SHIFT_RULE_GATES = ("rx", "ry", "rz", "rzz", "cp")
+SHIFT_RULE_GATES = ("rx", "ry", "rz", "rzz", "cp", "rxx", "ryy")
 
 _lib = None
 _lock = threading.Lock()
@@ -47,7 +47,7 @@ _lock = threading.Lock()
 
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (plain -O2, no vectorisation tricks)."""
-    if force or not os.path.exists(_SO):
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
@@ -58,8 +58,7 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_SO):
-                build(force=False)
+            build(force=False)          # when missing or older than its source
             L = ctypes.CDLL(_SO)
             dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
             L.orc_gate_matrix.argtypes = [ctypes.c_int, ctypes.c_double, dp]

@@ -14,7 +14,8 @@
  *   - flat index j = sum_w b_w 2^(n-1-w): wire 0 is the most significant bit,
  *     the first factor of the ket (tensor form of section 7.1); pinned by the
  *     QFT listing equalling the unitary DFT;
- *   - RX/RY/RZ(t) = exp(-i t P/2), RZZ(t) = exp(-i t Z(x)Z/2);
+ *   - RX/RY/RZ(t) = exp(-i t P/2), RZZ(t) = exp(-i t Z(x)Z/2), and likewise
+ *     RXX(t) = exp(-i t X(x)X/2), RYY(t) = exp(-i t Y(x)Y/2);
  *   - CP(phi) = diag(1,1,1,e^{i phi}); CNOT flips the target where the control
  *     is 1; CZ negates |11>; SWAP exchanges the two wires;
  *   - a k-qubit matrix acts on an ordered wire list whose first wire is the
@@ -32,7 +33,7 @@ typedef double complex cplx;
 
 enum {
     ORC_H = 0, ORC_X, ORC_Y, ORC_Z, ORC_RX, ORC_RY, ORC_RZ,
-    ORC_CNOT, ORC_CZ, ORC_SWAP, ORC_CP, ORC_RZZ, ORC_UNITARY
+    ORC_CNOT, ORC_CZ, ORC_SWAP, ORC_CP, ORC_RZZ, ORC_UNITARY, ORC_RXX, ORC_RYY
 };
 
 /* Matrix of a named gate at angle theta, row-major, into U (size dim*dim).
@@ -83,6 +84,16 @@ int orc_gate_matrix(int op, double theta, double *U_interleaved)
         k = 2;
         U[0] = cexp(-I * theta / 2.0); U[5] = cexp(I * theta / 2.0);
         U[10] = cexp(I * theta / 2.0); U[15] = cexp(-I * theta / 2.0);
+        break;
+    case ORC_RXX:  /* c I - i s X(x)X: X(x)X exchanges |00>,|11> and |01>,|10> */
+        k = 2;
+        U[0] = c; U[5] = c; U[10] = c; U[15] = c;
+        U[0 * 4 + 3] = -I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = -I * s;
+        break;
+    case ORC_RYY:  /* c I - i s Y(x)Y: Y(x)Y = -1 on the |00>,|11> corners, +1 on |01>,|10> */
+        k = 2;
+        U[0] = c; U[5] = c; U[10] = c; U[15] = c;
+        U[0 * 4 + 3] = I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = I * s;
         break;
     default:
         return -1;

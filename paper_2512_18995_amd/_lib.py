@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdq.so")
 
 OPS = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "cnot": 7, "cz": 8, "swap": 9,
-       "cp": 10, "rzz": 11, "unitary": 12}
+       "cp": 10, "rzz": 11, "unitary": 12, "rxx": 13, "ryy": 14}
 SRC = {"none": 0, "param": 1, "data": 2}
 STATUS = {0: "DQ_OK", 1: "DQ_ERR_INVALID_ARG", 2: "DQ_ERR_UNSUPPORTED", 3: "DQ_ERR_WORKSPACE",
           4: "DQ_ERR_OUT_OF_RANGE", 5: "DQ_ERR_HIP", 6: "DQ_ERR_INTERNAL"}

@@ -15,7 +15,8 @@ namespace dq {
 // Internal op codes equal the public dq_op values.
 enum : int32_t {
     OP_H = 0, OP_X, OP_Y, OP_Z, OP_RX, OP_RY, OP_RZ, OP_CNOT, OP_CZ, OP_SWAP, OP_CP, OP_RZZ,
-    OP_UNITARY
+    OP_UNITARY,
+    OP_RXX, OP_RYY   // plan input only: expanded into basis changes around an RZZ
 };
 enum : int32_t { SRC_NONE = 0, SRC_PARAM = 1, SRC_DATA = 2 };
 

@@ -42,10 +42,12 @@ dq_status ok() {
         if (e_ != hipSuccess) return fail(DQ_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-bool is_rotation(int op) { return op == OP_RX || op == OP_RY || op == OP_RZ || op == OP_CP || op == OP_RZZ; }
+bool is_rotation(int op) {
+    return op == OP_RX || op == OP_RY || op == OP_RZ || op == OP_CP || op == OP_RZZ || op == OP_RXX || op == OP_RYY;
+}
 int arity(int op) {
     switch (op) {
-    case OP_CNOT: case OP_CZ: case OP_SWAP: case OP_CP: case OP_RZZ: return 2;
+    case OP_CNOT: case OP_CZ: case OP_SWAP: case OP_CP: case OP_RZZ: case OP_RXX: case OP_RYY: return 2;
     case OP_UNITARY: return -1;
     default: return 1;
     }
@@ -1274,7 +1276,7 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     p->ndata = ndata;
     for (int64_t g = 0; g < ngates; ++g) {
         const dq_gate &G = gates[g];
-        if (G.op < DQ_OP_H || G.op > DQ_OP_UNITARY) {
+        if (G.op < DQ_OP_H || G.op > DQ_OP_RYY) {
             delete p;
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: unknown op %d", (long long)g, G.op);
         }
@@ -1319,6 +1321,29 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
         D.idx = G.idx;
         D.scale = G.scale;
         D.mat_off = -1;
+        if (G.op == DQ_OP_RXX || G.op == DQ_OP_RYY) {
+            // exp(-i t P(x)P / 2) = (V(x)V)^dagger exp(-i t Z(x)Z / 2) (V(x)V) with
+            // V Z-diagonalising P: H for X (H Z H = X), RX(pi/2) for Y
+            // (RX(pi/2)^dagger Z RX(pi/2) = Y); the RZZ carries the angle and
+            // its gradient, the basis changes are fixed
+            auto basis = [&](double sign) {
+                for (int i = 0; i < 2; ++i) {
+                    DGate B{};
+                    B.op = G.op == DQ_OP_RXX ? OP_H : OP_RX;
+                    B.nq = 1;
+                    B.bits[0] = D.bits[i];
+                    B.src = SRC_NONE;
+                    B.scale = G.op == DQ_OP_RXX ? 0.0 : sign * M_PI / 2;
+                    B.mat_off = -1;
+                    p->gates.push_back(B);
+                }
+            };
+            basis(1.0);
+            D.op = OP_RZZ;
+            p->gates.push_back(D);
+            basis(-1.0);
+            continue;
+        }
         if (G.op == DQ_OP_UNITARY) {
             if (!G.matrix) {
                 delete p;

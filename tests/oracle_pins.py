@@ -280,4 +280,26 @@ def pin_sampling():
     assert np.all(np.abs(counts - N * q) <= 5 * sd + 1), (counts, N * q)
 
 
+def pin_two_qubit_xy_rotations():
+    """RXX(t) and RYY(t) are the matrix exponentials exp(-i t P(x)P / 2)
+    (scipy's expm of the Kronecker product; first listed wire = most
+    significant bit), and their parameter-shift gradient equals central
+    differences in a small circuit."""
+    X = np.array([[0, 1], [1, 0]], complex)
+    Y = np.array([[0, -1j], [1j, 0]])
+    rng = np.random.default_rng(13)
+    for name, P in (("rxx", X), ("ryy", Y)):
+        for t in rng.uniform(-2 * np.pi, 2 * np.pi, 3):
+            _close(oracle.gate_matrix(name, t), expm(-0.5j * t * np.kron(P, P)), 1e-14, "%s(%.3f)" % (name, t))
+    n = 4
+    c = W.Circuit(n, [W.Gate("h", (q,)) for q in range(n)] + [W.Gate("ry", (1,), "param", 0),
+                  W.Gate("rxx", (0, 2), "param", 1), W.Gate("ryy", (3, 1), "param", 2), W.Gate("cnot", (2, 3)),
+                  W.Gate("ryy", (2, 0), "param", 3), W.Gate("rxx", (1, 3), "param", 4)], 5)
+    th = rng.uniform(0, 2 * np.pi, 5)
+    obs = [[(0.7, "ZXIY"), (-0.4, "YZZI")]]
+    gp, _ = oracle.grad_param_shift(c, th, None, obs, np.ones((1, 1)), 1)
+    gf, _ = oracle.grad_fd(c, th, None, obs, np.ones((1, 1)), 1)
+    _close(gp, gf, 1e-8, "shift vs central differences (rxx, ryy)")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -57,6 +57,23 @@ def _create(L, n, gates, nparams=0, ndata=0, dtype=0, opt=None):
     return st, h
 
 
+def test_unknown_op_and_xy_rotations(L):
+    """Op codes beyond the last one are rejected; RXX and RYY are planned as
+    basis changes around an RZZ (four more internal gates each)."""
+    arr, keep = L.gate_array([G("h", (0,))])
+    arr[0].op = 15
+    h = ctypes.c_void_p()
+    assert L.lib().dq_plan_create(ctypes.byref(h), 3, arr, 1, 0, 0, 0, None) == 1
+    assert "unknown op" in L.lib().dq_last_error().decode()
+    st, h = _create(L, 3, [G("rxx", (0, 2), "param", 0), G("ryy", (1, 0), "param", 1)], 2, 0)
+    assert st == 0
+    s = L.DqPlanStats()
+    assert L.lib().dq_plan_get_stats(h, ctypes.byref(s)) == 0
+    assert s.ngates == 10
+    L.lib().dq_plan_destroy(h)
+
+
+
 @pytest.mark.parametrize("n,gates,np_,nd,code", [
     (0, [], 0, 0, 4),                                         # nqubits out of range
     (35, [], 0, 0, 4),
@@ -67,6 +84,8 @@ def _create(L, n, gates, nparams=0, ndata=0, dtype=0, opt=None):
     (3, [G("ry", (0,), "data", 0)], 2, 0, 1),                 # data index without data
     (3, [G("h", (0,), "param", 0)], 2, 0, 1),                 # angle on a fixed gate
     (3, [G("unitary", (0, 1))], 0, 0, 1),                     # unitary without matrix
+    (3, [G("rxx", (0,), "param", 0)], 1, 0, 1),               # two-qubit rotation on one wire
+    (3, [G("ryy", (2, 2), "param", 0)], 1, 0, 1),             # repeated wire
 ])
 def test_plan_create_rejects(L, n, gates, np_, nd, code):
     st, h = _create(L, n, gates, np_, nd)

@@ -561,3 +561,29 @@ def test_large_states_against_references(jit):
             assert abs(g[k] - r) <= 1e-5 * scale, ("d/dtheta_%d, layout %s" % (k, layout), g[k], r)
         del st
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("jit", [False, True], ids=["interpreted", "compiled"])
+@pytest.mark.parametrize("n,batch,per_sample", [(6, 2, True), (11, 2, False)])
+def test_xx_yy_rotations_forward_and_adjoint(dtype, jit, n, batch, per_sample):
+    """RXX and RYY (planned as basis changes around an RZZ that carries the
+    angle) among one- and two-qubit gates: states against the oracle, which
+    applies their 4x4 matrices directly, and adjoint gradients (parameters
+    and data) against its parameter shift."""
+    rng = np.random.default_rng(800 + n)
+    ops = ("h", "rx", "ry", "rz", "cnot", "rxx", "ryy", "rzz")
+    c = W.random_circuit(rng, n, 8 * n, ops=ops, with_data=True)
+    assert any(g.op == "rxx" for g in c.gates) and any(g.op == "ryy" for g in c.gates)
+    params, data = W.random_params(rng, c, batch, per_sample)
+    obs = [W.random_pauli_sum(rng, n, 4), W.random_pauli_sum(rng, n, 2)]
+    w = rng.standard_normal((batch, len(obs)))
+    plan, st = gpu_forward(c, params, data, batch, dtype, True, jit=jit)
+    got = st.cpu().numpy()
+    for b in range(batch):
+        assert_state(got[b], oracle.state(c, params, data, b), dtype, 5 * len(c.gates), "sample %d" % b)
+    gp, gd = dq.adjoint_grad(plan, dq.Observable(n, obs), st, t64(params), t64(data), t64(w))
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w, batch, threads=8)
+    tol = 1e-6 if dtype == "c64" else 1e-12
+    normwise(gp.cpu().numpy(), rp, RTOL[dtype], tol, "d/dparams")
+    normwise(gd.cpu().numpy(), rd, RTOL[dtype], tol, "d/ddata")

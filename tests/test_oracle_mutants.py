@@ -35,6 +35,10 @@ MUTANTS = [
     ("subindex-order", "if ((a >> (k - 1 - t)) & 1)", "if ((a >> t) & 1)"),
     ("dropped-conj", "acc += conj(psi[j]) * phi[j];", "acc += psi[j] * phi[j];"),
     ("prob-wrong-half", "if (!(j & bit))", "if (j & bit)"),
+    ("rxx-sign", "U[0 * 4 + 3] = -I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = -I * s;",
+     "U[0 * 4 + 3] = I * s; U[1 * 4 + 2] = I * s; U[2 * 4 + 1] = I * s; U[3 * 4 + 0] = I * s;"),
+    ("ryy-as-rxx", "U[0 * 4 + 3] = I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = I * s;",
+     "U[0 * 4 + 3] = -I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = -I * s;"),
 ]
 
 

@@ -345,8 +345,9 @@ def main():
                     help="forward sweep as fused dense k-qubit blocks on the matrix cores")
     ap.add_argument("--passes", choices=["auto", "compiled", "interpreted"], default="auto",
                     help="tile passes compiled at plan time or interpreted (op lists read at run time); auto: "
-                         "compiled for the 32-qubit workload, whose 178 passes need 19 distinct kernels, "
-                         "interpreted for the others, whose passes rarely repeat")
+                         "compiled for every single-plan workload (the compiles fall in the untimed first "
+                         "warm-up step, reported as first_step_s, and are cached on disk); the multi-circuit "
+                         "workload always runs interpreted passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-layers", type=int, default=2)
@@ -384,7 +385,7 @@ def main():
     wl = W.config(cid)
     c = wl.circuit
     B = wl.batch
-    jit = args.passes == "compiled" or (args.passes == "auto" and args.workload in ("cfg1", "cfg5"))
+    jit = args.passes != "interpreted"
     plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits, dense_fuse=args.dense_fuse, jit=jit,
                    adj_tile_bits=args.adj_tile_bits, low_bits=args.low_bits, layout=args.layout)
     obs = dq.Observable(c.n, wl.observables)

@@ -588,7 +588,12 @@ constexpr int EXP_TM = 32;
 
 // Partial sums S_t = sum_j (-1)^{|j & z_t|} conj(psi_{j^x}) psi_j over this
 // block's share of the amplitudes, for up to EXP_TM terms of one X-mask
-// group.  DIAG (x = 0): the product is |psi_j|^2, real.
+// group.  DIAG (x = 0): the product is |psi_j|^2, real.  Otherwise the
+// indices pair up as (j, j^x) with bit h (the highest of x) clear in j: the
+// summand at j^x is the conjugate of the one at j times
+// sigma = (-1)^{|x & z_t|}, so a pair adds 2 s_j Re(c) when sigma = +1 and
+// 2 i s_j Im(c) when sigma = -1 (c = conj(psi_{j^x}) psi_j), and each
+// amplitude is loaded once per group.
 template <typename T, bool DIAG>
 __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t x, cptr<DTerm> terms, int c0,
                                              int nt, double *row, int eb, double (*red)[2 * EXP_TM]) {
@@ -601,29 +606,45 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
         ar[t] = 0.0;
         ai[t] = 0.0;
     }
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)eb * blockDim.x) {
-        const cx<T> a = p[j];
-        double pr, pi = 0.0;
-        if (DIAG) {
-            pr = (double)(a.x * a.x + a.y * a.y);
-        } else {
-            const cx<T> o = p[j ^ (int64_t)x];
-            pr = (double)(o.x * a.x + o.y * a.y);
-            pi = (double)(o.x * a.y - o.y * a.x);
-        }
+    if (DIAG) {
+        for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)eb * blockDim.x) {
+            const cx<T> a = p[j];
+            const double pr = (double)(a.x * a.x + a.y * a.y);
 #pragma unroll
-        for (int t = 0; t < EXP_TM; ++t) {
-            if (t < nt) {
-                const bool neg = __popcll((uint64_t)j & z[t]) & 1;
-                ar[t] += neg ? -pr : pr;
-                if (!DIAG) ai[t] += neg ? -pi : pi;
+            for (int t = 0; t < EXP_TM; ++t) {
+                if (t < nt) {
+                    const bool neg = __popcll((uint64_t)j & z[t]) & 1;
+                    ar[t] += neg ? -pr : pr;
+                }
+            }
+        }
+    } else {
+        const int h = 63 - __clzll((long long)x);   // x != 0
+        const int64_t lo = (int64_t(1) << h) - 1;
+        bool odd[EXP_TM];
+#pragma unroll
+        for (int t = 0; t < EXP_TM; ++t) odd[t] = t < nt && (__popcll(x & z[t]) & 1);
+        for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < (N >> 1); k += (int64_t)eb * blockDim.x) {
+            const int64_t j = ((k & ~lo) << 1) | (k & lo);
+            const cx<T> a = p[j];
+            const cx<T> o = p[j ^ (int64_t)x];
+            const double pr = (double)(o.x * a.x + o.y * a.y);
+            const double pi = (double)(o.x * a.y - o.y * a.x);
+#pragma unroll
+            for (int t = 0; t < EXP_TM; ++t) {
+                if (t < nt) {
+                    const bool neg = __popcll((uint64_t)j & z[t]) & 1;
+                    if (odd[t]) ai[t] += neg ? -pi : pi;
+                    else ar[t] += neg ? -pr : pr;
+                }
             }
         }
     }
 #pragma unroll
     for (int t = 0; t < EXP_TM; ++t) {
         if (t < nt) {
-            const double xr = wave_sum(ar[t]), xi = DIAG ? 0.0 : wave_sum(ai[t]);
+            const double xr = DIAG ? wave_sum(ar[t]) : 2.0 * wave_sum(ar[t]);
+            const double xi = DIAG ? 0.0 : 2.0 * wave_sum(ai[t]);
             if (lane == 0) {
                 red[wv][2 * t] = xr;
                 red[wv][2 * t + 1] = xi;

@@ -145,6 +145,9 @@ hipError_t launch_tile_adj(int dbl, const TileArgs &a, hipStream_t s);
 // resident single-wave workgroups of the adjoint tile kernel on the current device
 int tile_adj_capacity(int dbl, int R);
 // multi-circuit tile passes: entries describe one depth of every circuit
+// tile shapes the multi-circuit kernels are instantiated for (tiles.hip)
+inline bool multi_fwd_has(int dbl, int R) { return R == 3 || R == 4 || (R == 5 && !dbl); }
+inline bool multi_adj_has(int dbl, int R) { return R == 3 || (R == 4 && !dbl); }
 hipError_t launch_tile_fwd_multi(int dbl, int R, void *st, const void *ws, const MultiEntry *ents, int32_t nent,
                                  int64_t units, hipStream_t s);
 hipError_t launch_tile_adj_multi(int dbl, int R, void *st, void *ws, const MultiEntry *ents, int32_t nent,

@@ -11,6 +11,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -36,6 +38,30 @@ dq_status ok() {
     g_err.clear();
     return DQ_OK;
 }
+// No C++ exception crosses the C ABI: every entry point is a function-try-
+// block whose handler turns a host-side failure (std::bad_alloc from a plan's
+// tables, a missing map entry, ...) into DQ_ERR_INTERNAL and dq_last_error().
+dq_status fail_nothrow(const char *what) noexcept {
+    try {
+        g_err.assign(what);
+    } catch (...) {
+        g_err.clear();
+    }
+    return DQ_ERR_INTERNAL;
+}
+#define DQ_CATCH                                                                            \
+    catch (const std::bad_alloc &) {                                                        \
+        return fail_nothrow("host memory allocation failed");                               \
+    }                                                                                       \
+    catch (const std::exception &e_) {                                                      \
+        return fail_nothrow(e_.what());                                                     \
+    }                                                                                       \
+    catch (...) {                                                                           \
+        return fail_nothrow("unexpected C++ exception");                                    \
+    }
+#define DQ_CATCH_VOID \
+    catch (...) {     \
+    }
 #define DQ_HIP(call)                                                                        \
     do {                                                                                    \
         hipError_t e_ = (call);                                                             \
@@ -80,8 +106,10 @@ struct ProfScope {
     hipStream_t s;
     hipEvent_t a = nullptr;
     double flops = 0;
-    ProfScope(dq_plan_s &pl, int k, int nlaunch, double b, hipStream_t st) : p(pl), kind(k), nl(nlaunch), bytes(b), s(st) {
-        if (prof_on(p)) {
+    // timed = false: no events (the allocation-free entry point creates none)
+    ProfScope(dq_plan_s &pl, int k, int nlaunch, double b, hipStream_t st, bool timed = true)
+        : p(pl), kind(k), nl(nlaunch), bytes(b), s(st) {
+        if (timed && prof_on(p)) {
             a = prof_event(p);
             (void)hipEventRecord(a, s);
         }
@@ -837,14 +865,16 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
                 }
                 b += line;
             }
-            snprintf(line, sizeof line, "            dq::cx<%s> fl_{%s(1), %s(0)}, r_[%d];\n", T, T, T, regk.empty() ? 1 : (int)regk.size());
+            // the lane factor fl_ and the ratios r_ are formed in double and
+            // rounded once inside diag_run
+            snprintf(line, sizeof line, "            dq::C128 fl_{1.0, 0.0}, r_[%d];\n", regk.empty() ? 1 : (int)regk.size());
             b += line;
             std::vector<char> started(regk.size(), 0);
             for (int64_t j = i; j < e; ++j) {
                 const TOp &o = ops[j];
                 const long long sl = (long long)(o.slot - s0);
                 if (o.q0 < 6) {
-                    snprintf(line, sizeof line, "            fl_ = dq::cmul(fl_, dq::csel(((lane >> %d) & 1) != 0, dq::ldc(m, %lld), dq::ldc(m, %lld)));\n",
+                    snprintf(line, sizeof line, "            fl_ = dq::cmul(fl_, dq::widen(dq::csel(((lane >> %d) & 1) != 0, dq::ldc(m, %lld), dq::ldc(m, %lld))));\n",
                              o.q0, sl + 3, sl);
                 } else {
                     const size_t ri = (size_t)(std::find(regk.begin(), regk.end(), o.q0 - 6) - regk.begin());
@@ -852,7 +882,7 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
                     const std::string rv = "r_[" + std::to_string(ri) + "]";
                     const std::string ratio = "dq::cmul(d1, dq::cconj(d0))";
                     snprintf(line, sizeof line,
-                             "            { const auto d0 = dq::ldc(m, %lld), d1 = dq::ldc(m, %lld); fl_ = dq::cmul(fl_, d0); "
+                             "            { const auto d0 = dq::widen(dq::ldc(m, %lld)), d1 = dq::widen(dq::ldc(m, %lld)); fl_ = dq::cmul(fl_, d0); "
                              "%s = %s; }\n", sl, sl + 3, rv.c_str(),
                              (started[ri] ? "dq::cmul(" + rv + ", " + ratio + ")" : ratio).c_str());
                     started[ri] = 1;
@@ -943,9 +973,11 @@ dq_plan_s *plan_clone_base(const dq_plan_s &p) {
     return q;
 }
 
-dq_plan_s *search_layout(dq_plan_s *p) {
+dq_plan_s *search_layout(dq_plan_s *p_in) {
+    std::unique_ptr<dq_plan_s> canon(p_in), chosen;   // the canonical plan; the best relabelled one
+    const dq_plan_s *const p = canon.get();
     const int64_t state_bytes = (int64_t)(p->dbl ? 16 : 8) << p->n;
-    if (!p->opt.fusion || p->R_fwd < 2 || p->n < 16 || state_bytes < (int64_t(128) << 20)) return p;
+    if (!p->opt.fusion || p->R_fwd < 2 || p->n < 16 || state_bytes < (int64_t(128) << 20)) return canon.release();
     const std::vector<DGate> base(p->gates.begin(), p->gates.begin() + p->user_gates);
     double best = plan_cost(*p);
     // k of the low bits 4, 3, .. (those pinned last first) move to k wires
@@ -968,7 +1000,7 @@ dq_plan_s *search_layout(dq_plan_s *p) {
                 perm[lows[j]] = tgt[k - 1 - j];
                 perm[tgt[k - 1 - j]] = lows[j];
             }
-            dq_plan_s *q = plan_clone_base(*p);
+            std::unique_ptr<dq_plan_s> q(plan_clone_base(*p));
             q->gates = base;
             for (DGate &g : q->gates)
                 for (int i = 0; i < g.nq; ++i) g.bits[i] = perm[g.bits[i]];
@@ -990,14 +1022,11 @@ dq_plan_s *search_layout(dq_plan_s *p) {
             q->layout_swaps = k;
             if (build_plan(*q) == DQ_OK && plan_cost(*q) < best) {
                 best = plan_cost(*q);
-                delete p;
-                p = q;
-            } else {
-                delete q;
+                chosen = std::move(q);
             }
         }
     }
-    return p;
+    return chosen ? chosen.release() : canon.release();
 }
 
 dq_status ensure_device(dq_plan_s &p, DevData **out) {
@@ -1141,7 +1170,7 @@ WsLayout layout(const dq_plan_s &p, const dq_obs_s *o, int64_t batch, int per_sa
 
 // ---------------------------------------------------------------- execution
 dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, void *lam, int64_t batch,
-                      const void *mats, int64_t mstride, double *partial, int wps, hipStream_t s) {
+                      const void *mats, int64_t mstride, double *partial, int wps, hipStream_t s, bool timed = true) {
     const double SB = state_bytes(p, batch);
     // consecutive launches of one kind share one pair of timing events, so
     // that profiling adds no work between them
@@ -1161,7 +1190,7 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
         }
         if (!ps || ps->kind != kind) {
             if (ps) ps->done();
-            ps.reset(new ProfScope(p, kind, 0, 0.0, s));
+            ps.reset(new ProfScope(p, kind, 0, 0.0, s, timed));
         }
         ps->nl += nl;
         ps->bytes += bytes;
@@ -1240,6 +1269,42 @@ dq_status check_sources(const dq_plan_s &p, const double *params, int64_t pstrid
     return DQ_OK;
 }
 
+// argument checks shared by the two apply entry points (host only)
+dq_status check_apply(const dq_plan_s *plan, const void *state, int64_t batch, const double *params,
+                      int64_t params_bstride, const double *data, int64_t data_bstride) {
+    if (!plan || !state) return fail(DQ_ERR_INVALID_ARG, "NULL plan or state");
+    dq_status st = check_batch(*plan, batch);
+    if (st != DQ_OK) return st;
+    return check_sources(*plan, params, params_bstride, data, data_bstride);
+}
+
+// Forward sweep of dq_apply_circuit with the gate-matrix blocks at `mats`:
+// prepare the matrices, write the start state, run the tile passes.
+dq_status apply_on_device(dq_plan_s &p, DevData &d, void *state, int64_t batch, const double *params,
+                          int64_t params_bstride, const double *data, int64_t data_bstride, int32_t from_zero,
+                          void *mats, int per_sample, hipStream_t s, bool timed) {
+    const bool fold = from_zero && p.has_fold;
+    const Program &prog = fold ? p.fwd_fold : p.fwd_full;
+    const int64_t bm = per_sample ? batch : 1;
+    const int64_t mstride = per_sample ? p.block : 0;
+    ProfScope pp(p, DQ_PROF_OTHER, 1, 0.0, s, timed);
+    hipError_t e = launch_prepare(p.dbl, d.gates, d.fixed, d.slots + prog.slot_lo, (int32_t)(prog.slot_hi - prog.slot_lo),
+                                  params, params_bstride, data, data_bstride, mats, p.block, bm, s);
+    if (e == hipSuccess)
+        e = launch_prepare_blocks(p.dbl, d.gates, d.fixed, d.blocks + prog.blk_lo, (int32_t)(prog.blk_hi - prog.blk_lo),
+                                  d.factors, params, params_bstride, data, data_bstride, mats, p.block, bm, s);
+    pp.done();
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
+    if (from_zero) {
+        ProfScope pi(p, DQ_PROF_INIT, 1, state_bytes(p, batch), s, timed);
+        if (fold) e = launch_init_product(p.dbl, state, p.n, batch, mats, mstride, d.fold, s);
+        else e = launch_init_zero(p.dbl, state, p.n, batch, s);
+        pi.done();
+    }
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "init: %s", hipGetErrorString(e));
+    return run_program(p, d, prog, state, nullptr, batch, mats, mstride, nullptr, 0, s, timed);
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -1249,7 +1314,7 @@ const char *dq_last_error(void) { return g_err.c_str(); }
 int32_t dq_version(void) { return DQ_VERSION; }
 
 dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, int64_t ngates, int64_t nparams,
-                         int64_t ndata, dq_dtype dtype, const dq_options *opt) {
+                         int64_t ndata, dq_dtype dtype, const dq_options *opt) try {
     if (!out) return fail(DQ_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (nqubits < 1 || nqubits > DQ_MAX_QUBITS)
@@ -1268,7 +1333,7 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     if (o.tile_bits < 0 || o.tile_bits > 6) return fail(DQ_ERR_INVALID_ARG, "tile_bits %d outside 0..6", o.tile_bits);
     if (o.dense_fuse != 0 && o.dense_fuse != 4 && o.dense_fuse != 5)
         return fail(DQ_ERR_INVALID_ARG, "dense_fuse must be 0, 4 or 5 (got %d)", o.dense_fuse);
-    auto *p = new dq_plan_s();
+    std::unique_ptr<dq_plan_s> p(new dq_plan_s());
     p->n = nqubits;
     p->dbl = dtype == DQ_C128;
     p->opt = o;
@@ -1277,40 +1342,32 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     for (int64_t g = 0; g < ngates; ++g) {
         const dq_gate &G = gates[g];
         if (G.op < DQ_OP_H || G.op > DQ_OP_RYY) {
-            delete p;
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: unknown op %d", (long long)g, G.op);
         }
         const int a = arity(G.op);
         if ((a > 0 && G.nq != a) || (a < 0 && (G.nq < 1 || G.nq > DQ_MAX_GATE_QUBITS))) {
-            delete p;
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: op %d with %d wires", (long long)g, G.op, G.nq);
         }
         for (int i = 0; i < G.nq; ++i) {
             if (G.wires[i] < 0 || G.wires[i] >= nqubits) {
-                delete p;
                 return fail(DQ_ERR_INVALID_ARG, "gate %lld: wire %d outside 0..%d", (long long)g, G.wires[i], nqubits - 1);
             }
             for (int j = 0; j < i; ++j)
                 if (G.wires[j] == G.wires[i]) {
-                    delete p;
                     return fail(DQ_ERR_INVALID_ARG, "gate %lld: wire %d repeated", (long long)g, G.wires[i]);
                 }
         }
         if (G.src < DQ_SRC_NONE || G.src > DQ_SRC_DATA) {
-            delete p;
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: bad angle source %d", (long long)g, G.src);
         }
         if (G.src != DQ_SRC_NONE && !is_rotation(G.op)) {
-            delete p;
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: op %d takes no angle", (long long)g, G.op);
         }
         if ((G.src == DQ_SRC_PARAM && (G.idx < 0 || G.idx >= nparams)) ||
             (G.src == DQ_SRC_DATA && (G.idx < 0 || G.idx >= ndata))) {
-            delete p;
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: source index %lld out of range", (long long)g, (long long)G.idx);
         }
         if (!std::isfinite(G.scale)) {
-            delete p;
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: non-finite scale", (long long)g);
         }
         DGate D{};
@@ -1346,7 +1403,6 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
         }
         if (G.op == DQ_OP_UNITARY) {
             if (!G.matrix) {
-                delete p;
                 return fail(DQ_ERR_INVALID_ARG, "gate %lld: UNITARY without a matrix", (long long)g);
             }
             const int dim = 1 << G.nq;
@@ -1358,16 +1414,15 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     p->user_gates = (int64_t)p->gates.size();
     dq_status st = build_plan(*p);
     if (st != DQ_OK) {
-        delete p;
         return st;
     }
-    if (o.layout == 0) p = search_layout(p);
+    if (o.layout == 0) p.reset(search_layout(p.release()));
     if (o.jit) jit_generate(*p);
-    *out = p;
+    *out = p.release();
     return ok();
-}
+} DQ_CATCH
 
-void dq_plan_destroy(dq_plan plan) {
+void dq_plan_destroy(dq_plan plan) try {
     if (!plan) return;
     for (hipEvent_t e : plan->evpool) (void)hipEventDestroy(e);
     for (auto &kv : plan->dev) {
@@ -1379,9 +1434,9 @@ void dq_plan_destroy(dq_plan plan) {
         }
     }
     delete plan;
-}
+} DQ_CATCH_VOID
 
-dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) {
+dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) try {
     if (!plan || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     dq_plan_stats s{};
     s.nqubits = plan->n;
@@ -1415,9 +1470,9 @@ dq_status dq_plan_get_stats(dq_plan plan, dq_plan_stats *out) {
     }
     *out = s;
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_plan_describe(dq_plan plan, char *buf, size_t cap, size_t *needed) {
+dq_status dq_plan_describe(dq_plan plan, char *buf, size_t cap, size_t *needed) try {
     if (!plan) return fail(DQ_ERR_INVALID_ARG, "NULL plan");
     std::string t;
     char line[256];
@@ -1455,9 +1510,9 @@ dq_status dq_plan_describe(dq_plan plan, char *buf, size_t cap, size_t *needed) 
         buf[n] = 0;
     }
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_plan_jit_source(dq_plan plan, int32_t index, char *buf, size_t cap, size_t *needed, int32_t *count) {
+dq_status dq_plan_jit_source(dq_plan plan, int32_t index, char *buf, size_t cap, size_t *needed, int32_t *count) try {
     if (!plan) return fail(DQ_ERR_INVALID_ARG, "NULL plan");
     if (count) *count = (int32_t)plan->jsrcs.size();
     if (index < 0) return ok();
@@ -1471,10 +1526,10 @@ dq_status dq_plan_jit_source(dq_plan plan, int32_t index, char *buf, size_t cap,
         buf[n] = 0;
     }
     return ok();
-}
+} DQ_CATCH
 
 dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms, const int64_t *obs_offsets,
-                        int32_t nobs) {
+                        int32_t nobs) try {
     if (!out) return fail(DQ_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (nqubits < 1 || nqubits > DQ_MAX_QUBITS) return fail(DQ_ERR_OUT_OF_RANGE, "nqubits %d", nqubits);
@@ -1486,7 +1541,7 @@ dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms
     if (nterms > 0 && !terms) return fail(DQ_ERR_INVALID_ARG, "terms is NULL");
     if (nterms > (1 << 20)) return fail(DQ_ERR_OUT_OF_RANGE, "too many terms");
     const uint64_t valid = nqubits >= 64 ? ~0ull : ((1ull << nqubits) - 1);
-    auto *o = new dq_obs_s();
+    std::unique_ptr<dq_obs_s> o(new dq_obs_s());
     o->n = nqubits;
     o->nobs = nobs;
     struct Tm { uint64_t x, z; double c; int obs; };
@@ -1495,11 +1550,9 @@ dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms
         for (int64_t t = obs_offsets[ob]; t < obs_offsets[ob + 1]; ++t) {
             const dq_pauli_term &T = terms[t];
             if ((T.xmask | T.zmask) & ~valid) {
-                delete o;
                 return fail(DQ_ERR_INVALID_ARG, "term %lld touches a wire >= %d", (long long)t, nqubits);
             }
             if (!std::isfinite(T.coef)) {
-                delete o;
                 return fail(DQ_ERR_INVALID_ARG, "term %lld: non-finite coefficient", (long long)t);
             }
             uint64_t px = 0, pz = 0;   // wire w -> physical bit n-1-w
@@ -1521,11 +1574,11 @@ dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms
         const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
         o->terms.push_back(DTerm{all[i].z, all[i].c * re[ny], all[i].c * im[ny], all[i].obs, 0});
     }
-    *out = o;
+    *out = o.release();
     return ok();
-}
+} DQ_CATCH
 
-void dq_obs_destroy(dq_obs obs) {
+void dq_obs_destroy(dq_obs obs) try {
     if (!obs) return;
     for (auto &kv : obs->dev) {
         int cur = 0;
@@ -1536,9 +1589,9 @@ void dq_obs_destroy(dq_obs obs) {
         }
     }
     delete obs;
-}
+} DQ_CATCH_VOID
 
-dq_status dq_workspace_size(dq_plan plan, dq_obs obs, int64_t batch, int32_t per_sample, int32_t grad, size_t *bytes) {
+dq_status dq_workspace_size(dq_plan plan, dq_obs obs, int64_t batch, int32_t per_sample, int32_t grad, size_t *bytes) try {
     if (!plan || !bytes) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     if (grad < 0 || grad > 2) return fail(DQ_ERR_INVALID_ARG, "grad must be 0, 1 or 2");
     if (grad && !obs) return fail(DQ_ERR_INVALID_ARG, "the adjoint needs an observable");
@@ -1546,9 +1599,9 @@ dq_status dq_workspace_size(dq_plan plan, dq_obs obs, int64_t batch, int32_t per
     if (st != DQ_OK) return st;
     *bytes = layout(*plan, obs, batch, per_sample ? 1 : 0, grad).total;
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_state_init(dq_plan plan, void *state, int64_t batch, const void *init, void *stream) {
+dq_status dq_state_init(dq_plan plan, void *state, int64_t batch, const void *init, void *stream) try {
     if (!plan || !state) return fail(DQ_ERR_INVALID_ARG, "NULL plan or state");
     dq_status st = check_batch(*plan, batch);
     if (st != DQ_OK) return st;
@@ -1556,51 +1609,27 @@ dq_status dq_state_init(dq_plan plan, void *state, int64_t batch, const void *in
                         : launch_init_zero(plan->dbl, state, plan->n, batch, (hipStream_t)stream);
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "state init: %s", hipGetErrorString(e));
     return ok();
-}
+} DQ_CATCH
 
 dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const double *params, int64_t params_bstride,
                            const double *data, int64_t data_bstride, int32_t from_zero, void *ws, size_t ws_bytes,
-                           void *stream) {
-    if (!plan || !state) return fail(DQ_ERR_INVALID_ARG, "NULL plan or state");
-    dq_status st = check_batch(*plan, batch);
+                           void *stream) try {
+    dq_status st = check_apply(plan, state, batch, params, params_bstride, data, data_bstride);
     if (st != DQ_OK) return st;
-    if ((st = check_sources(*plan, params, params_bstride, data, data_bstride)) != DQ_OK) return st;
     const int per_sample = (params_bstride != 0 || data_bstride != 0) ? 1 : 0;
     const WsLayout L = layout(*plan, nullptr, batch, per_sample, 0);
     if (!ws || ws_bytes < L.total)
         return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : 0);
     DevData *d = nullptr;
     if ((st = ensure_device(*plan, &d)) != DQ_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    const bool fold = from_zero && plan->has_fold;
-    const Program &prog = fold ? plan->fwd_fold : plan->fwd_full;
-    const int64_t bm = per_sample ? batch : 1;
-    const int64_t mstride = per_sample ? plan->block : 0;
-    char *w = (char *)ws;
-    void *mats = w + L.mats;
-    ProfScope pp(*plan, DQ_PROF_OTHER, 1, 0.0, s);
-    hipError_t e = launch_prepare(plan->dbl, d->gates, d->fixed, d->slots + prog.slot_lo,
-                                  (int32_t)(prog.slot_hi - prog.slot_lo), params, params_bstride, data, data_bstride,
-                                  mats, plan->block, bm, s);
-    if (e == hipSuccess)
-        e = launch_prepare_blocks(plan->dbl, d->gates, d->fixed, d->blocks + prog.blk_lo,
-                                  (int32_t)(prog.blk_hi - prog.blk_lo), d->factors, params, params_bstride, data,
-                                  data_bstride, mats, plan->block, bm, s);
-    pp.done();
-    if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
-    if (from_zero) {
-        ProfScope pi(*plan, DQ_PROF_INIT, 1, state_bytes(*plan, batch), s);
-        if (fold) e = launch_init_product(plan->dbl, state, plan->n, batch, mats, mstride, d->fold, s);
-        else e = launch_init_zero(plan->dbl, state, plan->n, batch, s);
-        pi.done();
-    }
-    if (e != hipSuccess) return fail(DQ_ERR_HIP, "init: %s", hipGetErrorString(e));
-    if ((st = run_program(*plan, *d, prog, state, nullptr, batch, mats, mstride, nullptr, 0, s)) != DQ_OK) return st;
+    if ((st = apply_on_device(*plan, *d, state, batch, params, params_bstride, data, data_bstride, from_zero,
+                              (char *)ws + L.mats, per_sample, (hipStream_t)stream, true)) != DQ_OK)
+        return st;
     return ok();
-}
+} DQ_CATCH
 
 dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, double *out, void *ws,
-                    size_t ws_bytes, void *stream) {
+                    size_t ws_bytes, void *stream) try {
     if (!plan || !obs || !state || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     if (obs->n != plan->n) return fail(DQ_ERR_INVALID_ARG, "observable is for %d qubits, plan for %d", obs->n, plan->n);
     dq_status st = check_batch(*plan, batch);
@@ -1621,7 +1650,7 @@ dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, 
     pe.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "expval: %s", hipGetErrorString(e));
     return ok();
-}
+} DQ_CATCH
 
 namespace {
 // blocks per outcome of the probability reduction
@@ -1631,7 +1660,7 @@ int64_t probs_blocks(const dq_plan_s &p, int32_t nwires) {
 }
 }  // namespace
 
-dq_status dq_probs_workspace_size(dq_plan plan, int64_t batch, int32_t nwires, size_t *bytes) {
+dq_status dq_probs_workspace_size(dq_plan plan, int64_t batch, int32_t nwires, size_t *bytes) try {
     if (!plan || !bytes) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     dq_status st = check_batch(*plan, batch);
     if (st != DQ_OK) return st;
@@ -1639,10 +1668,10 @@ dq_status dq_probs_workspace_size(dq_plan plan, int64_t batch, int32_t nwires, s
         return fail(DQ_ERR_INVALID_ARG, "nwires %d outside 1..%d", nwires, std::min(PROB_MAXW, (int)plan->n));
     *bytes = align256((size_t)batch * ((size_t)1 << nwires) * (size_t)probs_blocks(*plan, nwires) * sizeof(double));
     return ok();
-}
+} DQ_CATCH
 
 dq_status dq_probs(dq_plan plan, const void *state, int64_t batch, const int32_t *wires, int32_t nwires, double *out,
-                   void *ws, size_t ws_bytes, void *stream) {
+                   void *ws, size_t ws_bytes, void *stream) try {
     if (!plan || !state || !wires || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     size_t need = 0;
     dq_status st = dq_probs_workspace_size(plan, batch, nwires, &need);
@@ -1668,10 +1697,10 @@ dq_status dq_probs(dq_plan plan, const void *state, int64_t batch, const int32_t
     pr.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "probs: %s", hipGetErrorString(e));
     return ok();
-}
+} DQ_CATCH
 
 dq_status dq_sample(const double *p, int64_t batch, int32_t nout, const double *u, int32_t shots, int64_t *out,
-                    void *stream) {
+                    void *stream) try {
     if (!p || !u || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     if (batch < 1 || batch > 65535) return fail(DQ_ERR_OUT_OF_RANGE, "batch %lld outside 1..65535", (long long)batch);
     if (nout < 1 || nout > (1 << 20)) return fail(DQ_ERR_INVALID_ARG, "nout %d outside 1..2^20", nout);
@@ -1680,12 +1709,12 @@ dq_status dq_sample(const double *p, int64_t batch, int32_t nout, const double *
     const hipError_t e = launch_sample(p, batch, nout, u, shots, out, (hipStream_t)stream);
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "sample: %s", hipGetErrorString(e));
     return ok();
-}
+} DQ_CATCH
 
 dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, const double *params,
                           int64_t params_bstride, const double *data, int64_t data_bstride, const double *grad_out,
                           double *grad_params, double *grad_data, int32_t preserve_state, void *ws, size_t ws_bytes,
-                          void *stream) {
+                          void *stream) try {
     if (!plan || !obs || !state || !grad_out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     if (obs->n != plan->n) return fail(DQ_ERR_INVALID_ARG, "observable is for %d qubits, plan for %d", obs->n, plan->n);
     if (plan->nparams > 0 && !grad_params) return fail(DQ_ERR_INVALID_ARG, "grad_params is NULL");
@@ -1755,15 +1784,15 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, 
     }
     pf.done();
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_profile_enable(dq_plan plan, int32_t on) {
+dq_status dq_profile_enable(dq_plan plan, int32_t on) try {
     if (!plan) return fail(DQ_ERR_INVALID_ARG, "NULL plan");
     plan->prof = on != 0;
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset) {
+dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset) try {
     if (!plan || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     for (const auto &r : plan->precs) {
         DQ_HIP(hipEventSynchronize(r.b));
@@ -1779,7 +1808,7 @@ dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset) {
     *out = plan->acc;
     if (reset) plan->acc = dq_profile{};
     return ok();
-}
+} DQ_CATCH
 
 // ================================================================ uneven batches
 }  // extern "C"
@@ -1880,26 +1909,22 @@ dq_status ensure_multi(dq_multi_s &m, dq_multi_s::Dev **out) {
 
 extern "C" {
 
-dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs, int32_t nplans) {
+dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs, int32_t nplans) try {
     if (!out || !plans || !obs || nplans < 1) return fail(DQ_ERR_INVALID_ARG, "need plans, observables and nplans >= 1");
     *out = nullptr;
-    auto *m = new dq_multi_s();
+    std::unique_ptr<dq_multi_s> m(new dq_multi_s());
     m->dbl = plans[0] ? plans[0]->dbl : 0;
     for (int c = 0; c < nplans; ++c) {
         if (!plans[c] || !obs[c]) {
-            delete m;
             return fail(DQ_ERR_INVALID_ARG, "circuit %d: NULL plan or observable", c);
         }
         if (plans[c]->dbl != m->dbl) {
-            delete m;
             return fail(DQ_ERR_INVALID_ARG, "circuit %d: dtype differs from circuit 0", c);
         }
         if (plans[c]->ndata > 0) {
-            delete m;
             return fail(DQ_ERR_UNSUPPORTED, "circuit %d: data-encoded gates are not supported in a multi-plan", c);
         }
         if (obs[c]->n != plans[c]->n) {
-            delete m;
             return fail(DQ_ERR_INVALID_ARG, "circuit %d: observable for %d qubits, plan for %d", c, obs[c]->n, plans[c]->n);
         }
         m->plans.push_back(plans[c]);
@@ -1926,8 +1951,11 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
         m->lay.push_back(L);
         m->ws_total += align256(L.total);
         const Program &f = p->has_fold ? p->fwd_fold : p->fwd_full;
+        // batched: pure tile programs of the common shape, for which the
+        // multi-circuit kernels exist; the rest take the single-plan path
         m->batched.push_back(p->R_fwd > 0 && p->R_fwd == m->R_fwd && p->R_adj == m->R_adj && tile_only(f, m->R_fwd) &&
-                             tile_only(p->adj, m->R_adj));
+                             tile_only(p->adj, m->R_adj) && multi_fwd_has(m->dbl, m->R_fwd) &&
+                             multi_adj_has(m->dbl, m->R_adj));
     }
     // depth tables
     const double tot_bytes = (double)m->st_total * (double)amp;   // all circuits' states
@@ -1964,11 +1992,11 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
             }
         }
     }
-    *out = m;
+    *out = m.release();
     return ok();
-}
+} DQ_CATCH
 
-void dq_multi_destroy(dq_multi m) {
+void dq_multi_destroy(dq_multi m) try {
     if (!m) return;
     for (auto &kv : m->dev) {
         int cur = 0;
@@ -1979,10 +2007,10 @@ void dq_multi_destroy(dq_multi m) {
         }
     }
     delete m;
-}
+} DQ_CATCH_VOID
 
 dq_status dq_multi_layout(dq_multi m, int64_t *state_amps, int64_t *param_count, int64_t *nout, int64_t *state_off,
-                          int64_t *param_off, int64_t *out_off) {
+                          int64_t *param_off, int64_t *out_off) try {
     if (!m) return fail(DQ_ERR_INVALID_ARG, "NULL multi-plan");
     if (state_amps) *state_amps = m->st_total;
     if (param_count) *param_count = m->par_total;
@@ -1993,15 +2021,15 @@ dq_status dq_multi_layout(dq_multi m, int64_t *state_amps, int64_t *param_count,
         if (out_off) out_off[c] = m->out_off[c];
     }
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_multi_workspace_size(dq_multi m, size_t *bytes) {
+dq_status dq_multi_workspace_size(dq_multi m, size_t *bytes) try {
     if (!m || !bytes) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     *bytes = m->ws_total;
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_multi_batched(dq_multi m, int32_t *batched, int32_t *count) {
+dq_status dq_multi_batched(dq_multi m, int32_t *batched, int32_t *count) try {
     if (!m) return fail(DQ_ERR_INVALID_ARG, "NULL multi-plan");
     int32_t k = 0;
     for (size_t c = 0; c < m->plans.size(); ++c) {
@@ -2010,9 +2038,9 @@ dq_status dq_multi_batched(dq_multi m, int32_t *batched, int32_t *count) {
     }
     if (count) *count = k;
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *ws, size_t ws_bytes, void *stream) {
+dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *ws, size_t ws_bytes, void *stream) try {
     if (!m || !states) return fail(DQ_ERR_INVALID_ARG, "NULL multi-plan or states");
     if (m->par_total > 0 && !params) return fail(DQ_ERR_INVALID_ARG, "params is NULL");
     if (!ws || ws_bytes < m->ws_total) return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed", m->ws_total);
@@ -2047,9 +2075,9 @@ dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *w
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi tile pass: %s", hipGetErrorString(e));
     }
     return ok();
-}
+} DQ_CATCH
 
-dq_status dq_multi_expval(dq_multi m, const void *states, double *out, void *ws, size_t ws_bytes, void *stream) {
+dq_status dq_multi_expval(dq_multi m, const void *states, double *out, void *ws, size_t ws_bytes, void *stream) try {
     if (!m || !states || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     if (!ws || ws_bytes < m->ws_total) return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed", m->ws_total);
     const size_t amp = m->dbl ? 16 : 8;
@@ -2059,10 +2087,10 @@ dq_status dq_multi_expval(dq_multi m, const void *states, double *out, void *ws,
         if (st != DQ_OK) return st;
     }
     return ok();
-}
+} DQ_CATCH
 
 dq_status dq_multi_adjoint_grad(dq_multi m, void *states, const double *params, const double *grad_out,
-                                double *grad_params, void *ws, size_t ws_bytes, void *stream) {
+                                double *grad_params, void *ws, size_t ws_bytes, void *stream) try {
     if (!m || !states || !grad_out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     if (m->par_total > 0 && (!params || !grad_params)) return fail(DQ_ERR_INVALID_ARG, "params / grad_params is NULL");
     if (!ws || ws_bytes < m->ws_total) return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed", m->ws_total);
@@ -2115,6 +2143,6 @@ dq_status dq_multi_adjoint_grad(dq_multi m, void *states, const double *params, 
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi grad reduce: %s", hipGetErrorString(e));
     }
     return ok();
-}
+} DQ_CATCH
 
 }  // extern "C"

@@ -885,6 +885,14 @@ __device__ __forceinline__ void op_s(cx<T> (&v)[NS][NR], cptr<cx<T>> m, int lane
 // first (up to) three register bits are built as a product tree of at most
 // eight values and applied in one multiply per amplitude; each further bit
 // multiplies its ratio into the amplitudes where it is set.
+//
+// fl, r and the product tree are formed in double precision from the
+// state-precision matrix entries and rounded once: a factor depends only on
+// the lane's bits, so every amplitude that shares them (a 1/64 slice of the
+// state) gets the same factor, and rounding errors of a single-precision
+// product would add coherently over the whole slice (for a run of about 20
+// gates, each of the 64 factors would carry about sqrt(20) roundings instead
+// of one, the same error on millions of amplitudes).
 template <int... KS> constexpr int pack_at(int j) {
     const int ks[] = {KS..., 0};
     return ks[j];
@@ -903,22 +911,27 @@ template <int... KS> constexpr int pack_mask(int j) {   // bits of the first j e
     return mk;
 }
 
+template <typename T> __device__ __forceinline__ C128 widen(cx<T> a) { return C128{(double)a.x, (double)a.y}; }
+template <typename T> __device__ __forceinline__ cx<T> narrow(C128 a) { return cx<T>{(T)a.x, (T)a.y}; }
+
 template <typename T, int NS, int NR, int... KS>
-__device__ __forceinline__ void diag_run(cx<T> (&v)[NS][NR], cx<T> fl, const cx<T> *r) {
+__device__ __forceinline__ void diag_run(cx<T> (&v)[NS][NR], C128 fl, const C128 *r) {
     using V = cx<T>;
     constexpr int k = sizeof...(KS);
     constexpr int kt = k < 3 ? k : 3;              // bits covered by the factor table
-    V f[1 << kt];
-    f[0] = fl;
+    C128 fd[1 << kt];
+    fd[0] = fl;
     static_for<0, kt>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         // f is indexed by the compacted bits of the table (bit j of the
         // index = register bit KS[j])
         static_for<0, (1 << j)>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            f[i | (1 << j)] = cmul(f[i], r[j]);
+            fd[i | (1 << j)] = cmul(fd[i], r[j]);
         });
     });
+    V f[1 << kt];
+    static_for<0, (1 << kt)>([&](auto ic) { f[decltype(ic)::value] = narrow<T>(fd[decltype(ic)::value]); });
     DQ_SF(NR, {
         constexpr int c = pack_compact<KS...>(i, kt);
         DQ_NS({ v[s_][i] = cmul(f[c], v[s_][i]); });
@@ -927,8 +940,9 @@ __device__ __forceinline__ void diag_run(cx<T> (&v)[NS][NR], cx<T> fl, const cx<
     static_for<kt, k>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         constexpr int kj = pack_at<KS...>(j);
+        const V rj = narrow<T>(r[j]);
         DQ_SF(NR, {
-            if constexpr ((i >> kj) & 1) { DQ_NS({ v[s_][i] = cmul(r[j], v[s_][i]); }); }
+            if constexpr ((i >> kj) & 1) { DQ_NS({ v[s_][i] = cmul(rj, v[s_][i]); }); }
         });
     });
 }

@@ -289,3 +289,90 @@ def test_jit_source_compiles_for_gfx950(L):
             dis = subprocess.run(["/opt/rocm/llvm/bin/llvm-objdump", "-d", f.name], capture_output=True, text=True).stdout
         assert name in dis
         assert not re.search(r"v_pk_(add|mul|fma)_f32", dis)
+
+
+_ALLOC_FAIL_SCRIPT = r"""
+import ctypes, resource, sys
+sys.path.insert(0, %r)
+import numpy as np
+from paper_2512_18995_amd import _lib
+L = _lib.lib()
+n = 4 << 20
+arr = (_lib.DqGate * n)()
+a = np.frombuffer(arr, dtype=np.int32).reshape(n, ctypes.sizeof(_lib.DqGate) // 4)
+a[:, 1] = 1                                  # H on wire 0, no angle source
+vm = [int(l.split()[1]) for l in open("/proc/self/status") if l.startswith("VmSize:")][0] * 1024
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+resource.setrlimit(resource.RLIMIT_AS, (vm + (96 << 20), hard))
+h = ctypes.c_void_p()
+st = L.dq_plan_create(ctypes.byref(h), 4, arr, n, 0, 0, 0, None)
+msg = L.dq_last_error().decode()
+resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+ok = ctypes.c_void_p()
+st2 = L.dq_plan_create(ctypes.byref(ok), 4, arr, 8, 0, 0, 0, None)
+print("|".join(map(str, (st, h.value is None, msg, st2))))
+"""
+
+
+def test_host_allocation_failure_returns_a_status(L, tmp_path):
+    """A host allocation that fails inside an entry point (here the gate
+    table of a 4M-gate plan under an address-space limit) comes back as
+    DQ_ERR_INTERNAL with a message: no C++ exception crosses the C ABI,
+    and the library stays usable afterwards."""
+    import subprocess
+    import sys
+    script = tmp_path / "alloc_fail.py"
+    script.write_text(_ALLOC_FAIL_SCRIPT % ROOT)
+    r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    st, null_handle, msg, st2 = r.stdout.strip().splitlines()[-1].split("|")
+    assert int(st) == 6 and null_handle == "True", r.stdout
+    assert "allocation" in msg
+    assert int(st2) == 0
+
+
+def _tile_steps(plan):
+    """(direction, R, compiled, operation count) of every register-tile step."""
+    out = []
+    for line in plan.describe().splitlines():
+        if " tile " not in line:
+            continue
+        R = int(re.search(r" R=(\d+)", line).group(1))
+        ops = line.split(" ops=")[1]
+        out.append((line.split()[0], R, " kernel=" in line, len(ops.split(";")) if ops else 0))
+    return out
+
+
+def test_benchmark_plans_have_no_interpreted_wide_tiles():
+    """Every plan the benchmark times (compiled passes): no register-tile
+    step with 64 amplitudes per lane runs interpreted (that kernel does not
+    exist: it kept its tile in scratch memory, and passes that fell back to
+    it ran for minutes), and every compiled pass stays within the compile
+    limit of 2048 operations x amplitudes per lane."""
+    import paper_2512_18995_amd as dq
+    import workloads as W
+    plans = [(W.config(c).circuit, W.config(c).dtype) for c in (1, 2, 3, 5)]
+    plans += [(W.qft(30), "c64"), (W.qft(32), "c64")]
+    for circuit, dtype in plans:
+        steps = _tile_steps(dq.Plan(circuit, dtype, jit=True))
+        assert steps
+        for d, R, compiled, nops in steps:
+            assert compiled or R <= 5, (circuit.n, d, R)
+            if compiled:
+                assert nops << R <= 2048, (circuit.n, d, R, nops)
+
+
+def test_multi_plan_runs_unbatched_shapes_on_the_single_plan_path():
+    """Circuits whose common tile shape has no multi-circuit kernel (an
+    8-qubit first circuit gives 2 register bits; compiled plans use 6) are
+    not batched: they take the single-plan path instead of failing at launch."""
+    import paper_2512_18995_amd as dq
+    import workloads as W
+    a, b = W.config(5, n=8, layers=2), W.config(5, n=12, layers=2)
+    obs = [dq.Observable(w.circuit.n, w.observables) for w in (a, b)]
+    m = dq.Multi([dq.Plan(a.circuit, "c64"), dq.Plan(b.circuit, "c64")], obs)
+    assert m.batched == [False, False]
+    m = dq.Multi([dq.Plan(b.circuit, "c64", jit=True), dq.Plan(b.circuit, "c64", jit=True)], [obs[1], obs[1]])
+    assert m.batched == [False, False]
+    m = dq.Multi([dq.Plan(b.circuit, "c64"), dq.Plan(b.circuit, "c64")], [obs[1], obs[1]])
+    assert m.batched == [True, True]

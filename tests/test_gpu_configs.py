@@ -1,10 +1,11 @@
 """Parity at the full benchmark sizes, with the plans the benchmark times
-(default tile shapes; passes compiled for the 10- and 32-qubit workloads,
-interpreted for the others): every output the oracle can
-compute in seconds is compared with it (all of them for the small
-workloads, sampled rows and gradient entries for the larger ones), and the
-32-qubit workload, beyond the oracle, is checked through properties that hold
-at any size and against the complex128 path and central differences."""
+(default tile shapes, passes compiled; the 16- and 20-qubit batches also
+with interpreted passes): every output the oracle can compute in seconds is
+compared with it (all of them for the small workloads, sampled rows and
+gradient entries for the larger ones), and the 32-qubit workload, beyond the
+oracle, is checked against closed forms of sampled amplitudes (one layer of
+its circuit; the Fourier transform of a basis state), against the complex128
+path and against central differences."""
 import numpy as np
 import pytest
 import torch
@@ -52,12 +53,13 @@ def test_config1_full_against_oracle():
     normwise(g, rp, RTOL["c128"], 1e-13, "gradient")
 
 
-def test_config2_all_rows_against_oracle():
+@pytest.mark.parametrize("jit", [True, False], ids=["compiled", "interpreted"])
+def test_config2_all_rows_against_oracle(jit):
     """16 qubits, 256 samples with per-sample data encoding, forward only:
     all 256 expectations against the oracle, states of sampled rows."""
     w = W.config(2)
     obs = dq.Observable(w.circuit.n, w.observables)
-    E, _, S = _run(_plan(w, jit=False), w, obs, grad=False, want_state=True)
+    E, _, S = _run(_plan(w, jit=jit), w, obs, grad=False, want_state=True)
     want = oracle.forward(w.circuit, w.params, w.data, w.observables, w.batch, threads=16)
     normwise(E, want, RTOL["c64"], 1e-6, "expvals of all 256 samples")
     for b in np.random.default_rng(2).choice(w.batch, 4, replace=False):
@@ -67,14 +69,15 @@ def test_config2_all_rows_against_oracle():
     assert np.max(np.abs(norms - 1.0)) < 1e-5
 
 
-def test_config3_sampled_against_oracle():
+@pytest.mark.parametrize("jit", [True, False], ids=["compiled", "interpreted"])
+def test_config3_sampled_against_oracle(jit):
     """20 qubits, 16 samples with their own parameters, TFIM observable:
     expectations of two samples and 12 seeded gradient entries of sample 0
     against the oracle; every sample's expectation and gradient row against
     the complex128 path."""
     w = W.config(3)
     obs = dq.Observable(w.circuit.n, w.observables)
-    E, g, _ = _run(_plan(w, jit=False), w, obs)
+    E, g, _ = _run(_plan(w, jit=jit), w, obs)
     rows = [0, w.batch - 1]
     want = oracle.forward(w.circuit, w.params, None, w.observables, w.batch, threads=2, samples=rows)
     normwise(E[rows], want, RTOL["c64"], 1e-6, "expvals of samples 0 and 15")
@@ -85,7 +88,7 @@ def test_config3_sampled_against_oracle():
                                     threads=16, samples=[0], gate_subset=gates)
     idx = [w.circuit.gates[i].idx for i in gates]
     normwise(g[0][idx], rp[0][idx], RTOL["c64"], 1e-7, "12 gradient entries of sample 0")
-    E2, g2, _ = _run(_plan(w, "c128", jit=False), w, obs)
+    E2, g2, _ = _run(_plan(w, "c128", jit=jit), w, obs)
     normwise(E, E2, RTOL["c64"], 1e-7, "expvals complex64 vs complex128")
     normwise(g, g2, RTOL["c64"], 1e-7, "gradients complex64 vs complex128")
 
@@ -143,4 +146,68 @@ def test_config5_32_qubits_properties():
         # and of the order of |E| here); rounding ~ 1e-15 sum|c| / h
         assert abs(fd - g2[k]) <= 5e-8 + 1e-5 * abs(g2[k]), (k, fd, g2[k])
     del st
+    torch.cuda.empty_cache()
+
+
+def _ring_preimage(j, n):
+    """Basis index that the CNOT ring CNOT(0,1), ..., CNOT(n-2,n-1),
+    CNOT(n-1,0) maps to j (wire w = bit n-1-w): the ring undone gate by
+    gate in reverse order (each CNOT is its own inverse)."""
+    bit = lambda x, w: (x >> (n - 1 - w)) & 1
+    for c in list(range(n))[::-1]:
+        t = (c + 1) % n
+        if bit(j, c):
+            j ^= 1 << (n - 1 - t)
+    return j
+
+
+def test_32_qubits_closed_forms_of_sampled_amplitudes():
+    """The 32-qubit workload's plan options (compiled passes, searched qubit
+    layout, low physical bits pinned into every tile) against closed forms
+    that do not go through the planner: (a) one layer of the workload's
+    circuit, RZ(phi_q) RY(theta_q) on every wire then the CNOT ring, is the
+    product state prod_q (e^{-i phi_q/2} cos(theta_q/2), e^{i phi_q/2}
+    sin(theta_q/2))[bit_q] read at the ring's preimage of each index;
+    (b) the Fourier transform of a basis state |k> has amplitudes
+    exp(2 pi i j k / 2^n) / 2^(n/2).  4096 sampled amplitudes each, so
+    every physical bit up to 31 is exercised."""
+    n = 32
+    N = 1 << n
+    rng = np.random.default_rng(32)
+    js = np.concatenate([rng.integers(0, N, 4090), [0, 1, N - 1, N - 2, N >> 1, (N >> 1) - 1]])
+    w = W.config(5, n=n, layers=1)
+    plan = dq.Plan(w.circuit, "c64", jit=True)
+    assert plan.stats()["layout_swaps"] > 0
+    st = plan.state(1, DEV)
+    dq.apply_circuit(plan, st, t64(w.params), None, from_zero=True)
+    got = st[0, torch.as_tensor(js, device=DEV)].cpu().numpy().astype(np.complex128)
+    th, ph = w.params[:n], w.params[n:2 * n]
+    u = np.stack([np.exp(-0.5j * ph) * np.cos(th / 2), np.exp(0.5j * ph) * np.sin(th / 2)], axis=1)
+    want = np.empty(len(js), dtype=np.complex128)
+    for i, j in enumerate(js.tolist()):
+        pre = _ring_preimage(j, n)
+        want[i] = np.prod([u[q, (pre >> (n - 1 - q)) & 1] for q in range(n)])
+    scale = np.sqrt(N)        # amplitudes of a unit state are ~2^(-n/2)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    print("one layer: max |err| / max |amp| = %.2e" % err, flush=True)
+    assert err <= 1e-5
+    assert abs(float(torch.linalg.vector_norm(st).item()) - 1.0) < 1e-5
+    del st, plan
+    torch.cuda.empty_cache()
+    c = W.qft(n)
+    plan = dq.Plan(c, "c64", jit=True)
+    st = plan.state(1, DEV)
+    k = 0x2545F491 % N
+    st.zero_()
+    st[0, k] = 1.0
+    dq.apply_circuit(plan, st, None, None, from_zero=False)
+    got = st[0, torch.as_tensor(js, device=DEV)].cpu().numpy().astype(np.complex128)
+    want = np.exp(2j * np.pi * ((js.astype(object) * k) % N).astype(np.float64) / N) / scale
+    err = float(np.max(np.abs(got - want)) * scale)
+    print("QFT|k>: max |err| x 2^(n/2) = %.2e" % err, flush=True)
+    # each amplitude passes through 528 gates, 16 of them phase products
+    # formed in complex64: relative error ~ 1e-6
+    assert err <= 2e-5
+    assert abs(float(torch.linalg.vector_norm(st).item()) - 1.0) < 1e-5
+    del st, plan
     torch.cuda.empty_cache()

@@ -11,11 +11,17 @@ import it; the product package never does.
   Pauli-string expectations (letters applied as ordinary gates), marginal
   probabilities.  Pure-state evolution is the equation of paper section 4.1;
   expectations and measurement follow the API overview of section 4.2.
-* this module: per-gate angles (``scale * source``), batching over samples,
-  and the two reference gradients -- the parameter-shift rule (exact for
-  gates exp(-i t G/2) whose generator G has eigenvalues +-1, and for the
-  controlled phase, whose generator has eigenvalues 0 and 1) and central
-  finite differences.  The adjoint method that the paper names for its
+* this module: per-gate angles (``scale * source``; U3 reads three
+  consecutive entries as theta, phi, lambda), batching over samples, and the
+  two reference gradients -- the parameter-shift rule and central finite
+  differences.  The two-term shift rule is exact for gates exp(-i t G/2)
+  whose generator G has eigenvalues +-1, for the controlled phase (generator
+  eigenvalues 0 and 1) and for each angle of U3 (each enters as such a
+  rotation, up to a global phase); the controlled rotations, whose
+  generator |1><1| (x) P has eigenvalues 0 and +-1, take the four-term rule
+  dE/dt = d+ [E(t + pi/2) - E(t - pi/2)] - d- [E(t + 3 pi/2) - E(t - 3 pi/2)],
+  d+- = (sqrt 2 +- 1) / (4 sqrt 2), exact for the two frequencies 1/2 and 1
+  that such a gate gives E.  The adjoint method that the paper names for its
   distributed simulator (section 7.2) is *not* re-implemented here: the
   oracle's gradients come from the definition of the derivative.
 * ``kron.py``: an independent numpy brute-force checker (tensor
@@ -37,9 +43,19 @@ _SRC = os.path.join(_HERE, "dq_oracle.c")
 _SO = os.path.join(_HERE, "_dq_oracle.so")
 
 OPCODE = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "cnot": 7, "cz": 8,
-          "swap": 9, "cp": 10, "rzz": 11, "unitary": 12, "rxx": 13, "ryy": 14}
+          "swap": 9, "cp": 10, "rzz": 11, "unitary": 12, "rxx": 13, "ryy": 14,
+          "u3": 15, "crx": 16, "cry": 17, "crz": 18}
 # gates whose derivative the two-term shift rule gives exactly
-SHIFT_RULE_GATES = ("rx", "ry", "rz", "rzz", "cp", "rxx", "ryy")
+SHIFT_RULE_GATES = ("rx", "ry", "rz", "rzz", "cp", "rxx", "ryy", "u3")
+# gates that need the four-term rule (generator eigenvalues 0, +-1)
+FOUR_TERM_GATES = ("crx", "cry", "crz")
+_D_PLUS = (np.sqrt(2.0) + 1.0) / (4.0 * np.sqrt(2.0))
+_D_MINUS = (np.sqrt(2.0) - 1.0) / (4.0 * np.sqrt(2.0))
+
+
+def n_angles(op: str) -> int:
+    return 3 if op == "u3" else 1
+
 
 _lib = None
 _lock = threading.Lock()
@@ -63,6 +79,8 @@ def lib():
             dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
             L.orc_gate_matrix.argtypes = [ctypes.c_int, ctypes.c_double, dp]
             L.orc_gate_matrix.restype = ctypes.c_int
+            L.orc_u3_matrix.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+            L.orc_u3_matrix.restype = None
             L.orc_apply.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, dp]
             L.orc_apply.restype = None
             L.orc_run.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp]
@@ -101,16 +119,18 @@ class _Encoded:
         self.gates = circuit.gates
 
     def angles(self, params, data, b: int) -> np.ndarray:
-        """theta_g = scale * (params[idx] | data[idx] | 1)."""
-        th = np.zeros(max(len(self.gates), 1))
+        """[G, 3]: theta_g,k = scale * (params[idx + k] | data[idx + k] | 1)
+        for the gate's k-th angle (k < 3 for U3, k = 0 otherwise)."""
+        th = np.zeros((max(len(self.gates), 1), 3))
         for i, g in enumerate(self.gates):
-            if g.src == "param":
-                p = np.asarray(params, float)
-                th[i] = g.scale * (p[b, g.idx] if p.ndim == 2 else p[g.idx])
-            elif g.src == "data":
-                th[i] = g.scale * float(np.asarray(data, float)[b, g.idx])
-            else:
-                th[i] = g.scale
+            for k in range(n_angles(g.op)):
+                if g.src == "param":
+                    p = np.asarray(params, float)
+                    th[i, k] = g.scale * (p[b, g.idx + k] if p.ndim == 2 else p[g.idx + k])
+                elif g.src == "data":
+                    th[i, k] = g.scale * float(np.asarray(data, float)[b, g.idx + k])
+                else:
+                    th[i, k] = g.scale
         return th
 
 
@@ -121,6 +141,7 @@ def _run_angles(enc: _Encoded, theta: np.ndarray, psi0: Optional[np.ndarray] = N
     else:
         psi[:] = psi0
     pv = psi.view(np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
     rc = lib().orc_run(enc.n, _dp(pv), len(enc.gates), _ip(enc.ops), _ip(enc.nq), _ip(enc.wires),
                        _dp(theta), _dp(enc.dense))
     if rc != 0:
@@ -129,6 +150,12 @@ def _run_angles(enc: _Encoded, theta: np.ndarray, psi0: Optional[np.ndarray] = N
 
 
 # ------------------------------------------------------------ public API
+def u3_matrix(theta: float, phi: float, lam: float) -> np.ndarray:
+    buf = np.zeros(8)
+    lib().orc_u3_matrix(float(theta), float(phi), float(lam), _dp(buf))
+    return buf.view(np.complex128).reshape(2, 2).copy()
+
+
 def gate_matrix(op: str, theta: float = 0.0) -> np.ndarray:
     buf = np.zeros(32)
     k = lib().orc_gate_matrix(OPCODE[op], float(theta), _dp(buf))
@@ -234,11 +261,13 @@ def _source_gates(circuit):
 def grad_param_shift(circuit, params, data, observables, weights, batch: int,
                      threads: Optional[int] = None, samples: Optional[Sequence[int]] = None,
                      gate_subset: Optional[Sequence[int]] = None):
-    """Vector-Jacobian product of L = sum_{b,o} w[b,o] E[b,o] by the two-term
-    parameter-shift rule, applied to every gate occurrence that reads a
-    parameter or a data entry:
-        dE/dtheta_g = (E(theta_g + pi/2) - E(theta_g - pi/2)) / 2,
-    chained through theta_g = scale * source.
+    """Vector-Jacobian product of L = sum_{b,o} w[b,o] E[b,o] by the
+    parameter-shift rule, applied to every angle of every gate occurrence
+    that reads a parameter or a data entry:
+        dE/dtheta = (E(theta + pi/2) - E(theta - pi/2)) / 2           (two-term)
+        dE/dtheta = d+ [E(theta + pi/2) - E(theta - pi/2)]
+                  - d- [E(theta + 3 pi/2) - E(theta - 3 pi/2)]         (controlled rotations)
+    chained through theta = scale * source.
     Returns (grad_params shaped like params, grad_data shaped like data)."""
     enc = _Encoded(circuit)
     w = np.asarray(weights, float).reshape(batch, len(observables))
@@ -248,33 +277,39 @@ def grad_param_shift(circuit, params, data, observables, weights, batch: int,
     samples = list(range(batch)) if samples is None else list(samples)
     gates = _source_gates(circuit) if gate_subset is None else list(gate_subset)
     for i in gates:
-        if circuit.gates[i].op not in SHIFT_RULE_GATES:
+        if circuit.gates[i].op not in SHIFT_RULE_GATES + FOUR_TERM_GATES:
             raise ValueError("no shift rule for %s" % circuit.gates[i].op)
 
-    jobs = [(b, i) for b in samples for i in gates]
+    jobs = [(b, i, k) for b in samples for i in gates for k in range(n_angles(circuit.gates[i].op))]
+
+    def L_at(b, th):
+        return float(np.dot(w[b], expvals(circuit.n, _run_angles(enc, th), observables)))
+
+    def shifted(b, th, i, k, s):
+        t2 = th.copy()
+        t2[i, k] += s
+        return L_at(b, t2)
 
     def one(job):
-        b, i = job
+        b, i, k = job
         th = enc.angles(params, data, b)
-        out = 0.0
-        for sgn in (+1.0, -1.0):
-            t2 = th.copy()
-            t2[i] += sgn * np.pi / 2
-            e = expvals(circuit.n, _run_angles(enc, t2), observables)
-            out += sgn * float(np.dot(w[b], e)) / 2.0
-        return out
+        if circuit.gates[i].op in FOUR_TERM_GATES:
+            a = shifted(b, th, i, k, np.pi / 2) - shifted(b, th, i, k, -np.pi / 2)
+            c = shifted(b, th, i, k, 3 * np.pi / 2) - shifted(b, th, i, k, -3 * np.pi / 2)
+            return _D_PLUS * a - _D_MINUS * c
+        return (shifted(b, th, i, k, np.pi / 2) - shifted(b, th, i, k, -np.pi / 2)) / 2.0
 
     with _pool(threads) as ex:
         vals = list(ex.map(one, jobs))
-    for (b, i), v in zip(jobs, vals):
+    for (b, i, k), v in zip(jobs, vals):
         g = circuit.gates[i]
         if g.src == "param":
             if gp.ndim == 2:
-                gp[b, g.idx] += g.scale * v
+                gp[b, g.idx + k] += g.scale * v
             else:
-                gp[g.idx] += g.scale * v
+                gp[g.idx + k] += g.scale * v
         else:
-            gd[b, g.idx] += g.scale * v
+            gd[b, g.idx + k] += g.scale * v
     return gp, gd
 
 

@@ -18,6 +18,12 @@
  *     RXX(t) = exp(-i t X(x)X/2), RYY(t) = exp(-i t Y(x)Y/2);
  *   - CP(phi) = diag(1,1,1,e^{i phi}); CNOT flips the target where the control
  *     is 1; CZ negates |11>; SWAP exchanges the two wires;
+ *   - U3(theta, phi, lambda) = [[cos(theta/2), -e^{i lambda} sin(theta/2)],
+ *     [e^{i phi} sin(theta/2), e^{i (phi + lambda)} cos(theta/2)]] (the
+ *     general one-qubit gate of the QResNet listing, section 4.3);
+ *   - CRX/CRY/CRZ(theta) on (control, target) = |0><0| (x) I + |1><1| (x)
+ *     R(theta) with R = RX/RY/RZ (the controlled rotations of the QCNN
+ *     listing and the controlled encoding of the QResNet listing);
  *   - a k-qubit matrix acts on an ordered wire list whose first wire is the
  *     most significant bit of the matrix index.
  *
@@ -33,7 +39,8 @@ typedef double complex cplx;
 
 enum {
     ORC_H = 0, ORC_X, ORC_Y, ORC_Z, ORC_RX, ORC_RY, ORC_RZ,
-    ORC_CNOT, ORC_CZ, ORC_SWAP, ORC_CP, ORC_RZZ, ORC_UNITARY, ORC_RXX, ORC_RYY
+    ORC_CNOT, ORC_CZ, ORC_SWAP, ORC_CP, ORC_RZZ, ORC_UNITARY, ORC_RXX, ORC_RYY,
+    ORC_U3, ORC_CRX, ORC_CRY, ORC_CRZ
 };
 
 /* Matrix of a named gate at angle theta, row-major, into U (size dim*dim).
@@ -95,6 +102,19 @@ int orc_gate_matrix(int op, double theta, double *U_interleaved)
         U[0] = c; U[5] = c; U[10] = c; U[15] = c;
         U[0 * 4 + 3] = I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = I * s;
         break;
+    case ORC_CRX: case ORC_CRY: case ORC_CRZ: {
+        /* identity on the control-0 block, the rotation on the control-1 block */
+        double R[8];
+        orc_gate_matrix(op == ORC_CRX ? ORC_RX : (op == ORC_CRY ? ORC_RY : ORC_RZ), theta, R);
+        k = 2;
+        U[0 * 4 + 0] = 1.0;
+        U[1 * 4 + 1] = 1.0;
+        U[2 * 4 + 2] = R[0] + I * R[1];
+        U[2 * 4 + 3] = R[2] + I * R[3];
+        U[3 * 4 + 2] = R[4] + I * R[5];
+        U[3 * 4 + 3] = R[6] + I * R[7];
+        break;
+    }
     default:
         return -1;
     }
@@ -104,6 +124,22 @@ int orc_gate_matrix(int op, double theta, double *U_interleaved)
         U_interleaved[2 * i + 1] = cimag(U[i]);
     }
     return k;
+}
+
+/* U3(theta, phi, lambda), row-major, into U (4 complex entries). */
+void orc_u3_matrix(double theta, double phi, double lambda, double *U_interleaved)
+{
+    double ch = cos(theta / 2.0);
+    double sh = sin(theta / 2.0);
+    cplx U[4];
+    U[0] = ch;
+    U[1] = -cexp(I * lambda) * sh;
+    U[2] = cexp(I * phi) * sh;
+    U[3] = cexp(I * (phi + lambda)) * ch;
+    for (int i = 0; i < 4; ++i) {
+        U_interleaved[2 * i] = creal(U[i]);
+        U_interleaved[2 * i + 1] = cimag(U[i]);
+    }
 }
 
 /* Apply a k-qubit matrix U (dim x dim, row-major, interleaved re/im) to the
@@ -149,9 +185,10 @@ void orc_apply(int n, double *psi_interleaved, int k, const int *wires, const do
 }
 
 /* Run a gate list on psi (caller initialises psi, normally to |0...0>).
- * ops[g], nq[g], wires[5*g .. 5*g+nq-1], theta[g]; unitary gates consume
- * their matrices from `dense` in order of appearance.  Returns 0, or -1 on an
- * unknown op. */
+ * ops[g], nq[g], wires[5*g .. 5*g+nq-1], angles theta[3*g .. 3*g+2] (one
+ * angle in theta[3*g] for every gate but U3, which takes theta, phi,
+ * lambda); unitary gates consume their matrices from `dense` in order of
+ * appearance.  Returns 0, or -1 on an unknown op. */
 int orc_run(int n, double *psi, int ngates, const int *ops, const int *nq, const int *wires,
             const double *theta, const double *dense)
 {
@@ -163,7 +200,11 @@ int orc_run(int n, double *psi, int ngates, const int *ops, const int *nq, const
             dense += 2 * dim * dim;
             continue;
         }
-        int k = orc_gate_matrix(ops[g], theta[g], U);
+        int k = 1;
+        if (ops[g] == ORC_U3)
+            orc_u3_matrix(theta[3 * g], theta[3 * g + 1], theta[3 * g + 2], U);
+        else
+            k = orc_gate_matrix(ops[g], theta[3 * g], U);
         if (k < 0 || k != nq[g])
             return -1;
         orc_apply(n, psi, k, wires + 5 * g, U);

@@ -5,7 +5,8 @@ C oracle:
 
 * rotation gates are matrix exponentials of their generators computed by
   ``scipy.linalg.expm`` (RX/RY/RZ(t) = exp(-i t P/2), RZZ(t) =
-  exp(-i t Z(x)Z/2)), controlled gates are built from projectors
+  exp(-i t Z(x)Z/2), the controlled rotations exp(-i t |1><1| (x) P / 2),
+  U3 as a phase times RZ RY RZ), controlled gates are built from projectors
   (|0><0| (x) I + |1><1| (x) V), the swap as (I + XX + YY + ZZ)/2 and the
   Hadamard as (X + Z)/sqrt(2);
 * a gate on wires (w_1..w_k) of an n-qubit register is embedded as a full
@@ -47,7 +48,19 @@ def named(op: str, theta: float = 0.0) -> np.ndarray:
         return (np.eye(4) + np.kron(PX, PX) + np.kron(PY, PY) + np.kron(PZ, PZ)) / 2.0
     if op == "rzz":
         return expm(-0.5j * theta * np.kron(PZ, PZ))
+    if op in ("rxx", "ryy"):
+        P = PAULI[op[1].upper()]
+        return expm(-0.5j * theta * np.kron(P, P))
+    if op in ("crx", "cry", "crz"):
+        return expm(-0.5j * theta * np.kron(P1, PAULI[op[2].upper()]))
     raise ValueError(op)
+
+
+def u3(theta: float, phi: float, lam: float) -> np.ndarray:
+    """e^{i (phi + lambda)/2} RZ(phi) RY(theta) RZ(lambda), each rotation a
+    matrix exponential of its generator."""
+    rz = lambda a: expm(-0.5j * a * PZ)
+    return np.exp(0.5j * (phi + lam)) * rz(phi) @ expm(-0.5j * theta * PY) @ rz(lam)
 
 
 def _perm_matrix(n: int, order) -> np.ndarray:
@@ -77,17 +90,22 @@ def embed_adjacent(U: np.ndarray, first: int, n: int) -> np.ndarray:
     return np.kron(np.kron(np.eye(1 << first), U), np.eye(1 << (n - first - k)))
 
 
-def gate_angle(g, params, data, b=0) -> float:
+def gate_angle(g, params, data, b=0, k=0) -> float:
     if g.src == "param":
         p = np.asarray(params, float)
-        return g.scale * (p[b, g.idx] if p.ndim == 2 else p[g.idx])
+        return g.scale * (p[b, g.idx + k] if p.ndim == 2 else p[g.idx + k])
     if g.src == "data":
-        return g.scale * float(np.asarray(data, float)[b, g.idx])
+        return g.scale * float(np.asarray(data, float)[b, g.idx + k])
     return g.scale
 
 
 def gate_full(g, n, params=None, data=None, b=0) -> np.ndarray:
-    U = np.asarray(g.matrix, complex) if g.op == "unitary" else named(g.op, gate_angle(g, params, data, b))
+    if g.op == "unitary":
+        U = np.asarray(g.matrix, complex)
+    elif g.op == "u3":
+        U = u3(*(gate_angle(g, params, data, b, k) for k in range(3)))
+    else:
+        U = named(g.op, gate_angle(g, params, data, b))
     return embed(U, list(g.wires), n)
 
 

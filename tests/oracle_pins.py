@@ -302,4 +302,85 @@ def pin_two_qubit_xy_rotations():
     _close(gp, gf, 1e-8, "shift vs central differences (rxx, ryy)")
 
 
+def pin_u3_gate():
+    """U3(theta, phi, lambda) = e^{i(phi+lambda)/2} RZ(phi) RY(theta) RZ(lambda)
+    (each rotation scipy's expm of its generator); special cases U3(t,0,0) =
+    RY(t), U3(0,0,l) = diag(1, e^{i l}), U3(pi/2, 0, pi) = H; unitary."""
+    rng = np.random.default_rng(14)
+    for _ in range(6):
+        a = rng.uniform(-2 * np.pi, 2 * np.pi, 3)
+        U = oracle.u3_matrix(*a)
+        _close(U, kron.u3(*a), 1e-14, "U3%s" % (tuple(np.round(a, 3)),))
+        _close(U.conj().T @ U, np.eye(2), 1e-14, "U3 unitary")
+        _close(oracle.u3_matrix(a[0], 0, 0), kron.named("ry", a[0]), 1e-15, "U3(t,0,0) = RY(t)")
+        _close(oracle.u3_matrix(0, 0, a[2]), np.diag([1, np.exp(1j * a[2])]), 1e-15, "U3(0,0,l)")
+    _close(oracle.u3_matrix(np.pi / 2, 0, np.pi), kron.named("h"), 1e-15, "U3(pi/2,0,pi) = H")
+
+
+def pin_controlled_rotations():
+    """CRX/CRY/CRZ(t) on (control, target) = exp(-i t |1><1| (x) P / 2)
+    (scipy's expm; control = most significant bit of the 4x4): the identity
+    where the control reads 0, the rotation where it reads 1; in a register
+    the control is the first listed wire."""
+    rng = np.random.default_rng(15)
+    for op in ("crx", "cry", "crz"):
+        for t in rng.uniform(-2 * np.pi, 2 * np.pi, 3):
+            U = oracle.gate_matrix(op, t)
+            _close(U, kron.named(op, t), 1e-14, "%s(%.3f)" % (op, t))
+            _close(U[:2, :2], np.eye(2), 0, "%s control-0 block" % op)
+            _close(U[2:, 2:], kron.named("r" + op[2], t), 1e-14, "%s control-1 block" % op)
+    # CRY with control wire 2 and target wire 0 of three, from |1 0 1> vs |0 0 1>
+    t = 1.1
+    c = W.Circuit(3, [W.Gate("x", (2,)), W.Gate("cry", (2, 0), "param", 0)], 1)
+    want = np.zeros(8, complex)
+    want[0b001], want[0b101] = np.cos(t / 2), np.sin(t / 2)
+    _close(oracle.state(c, [t]), want, 1e-15, "CRY(2 -> 0) with the control set")
+    c = W.Circuit(3, [W.Gate("cry", (2, 0), "param", 0)], 1)
+    _close(oracle.state(c, [t]), np.eye(8)[0], 0, "CRY(2 -> 0) with the control clear")
+
+
+def pin_u3_and_controlled_rotations_bruteforce():
+    """Random circuits with U3 and controlled rotations among the other
+    gates (parameters and data) at n <= 5 equal the Kronecker-embedded
+    product, with U3's three angles read from consecutive entries."""
+    rng = np.random.default_rng(16)
+    ops = ("h", "rx", "ry", "rz", "cnot", "cz", "u3", "crx", "cry", "crz", "rxx")
+    for n in (2, 3, 5):
+        for trial in range(3):
+            c = W.random_circuit(rng, n, 20, ops=ops, with_data=True)
+            P = c.n_params        # at least one U3 and one controlled rotation, whatever was drawn
+            extra = [W.Gate("u3", (n - 1,), "param", P), W.Gate(("crx", "cry", "crz")[trial], (n - 1, 0), "param", P + 3)]
+            c = W.Circuit(n, extra[:1] + c.gates + extra[1:], P + 4, c.n_data)
+            params, data = W.random_params(rng, c, 1)
+            _close(oracle.state(c, params, data), kron.state(c, params, data), 1e-12,
+                   "kron with u3 / cr n=%d trial %d" % (n, trial))
+
+
+def pin_four_term_shift_equals_fd():
+    """The four-term rule of the controlled rotations and the two-term rule
+    on each U3 angle equal central finite differences (parameters and
+    data), and a plain two-term rule would miss a controlled rotation's
+    derivative."""
+    rng = np.random.default_rng(17)
+    ops = ("h", "ry", "cnot", "u3", "crx", "cry", "crz")
+    for n in (2, 4):
+        c = W.random_circuit(rng, n, 16, ops=ops, with_data=True)
+        params, data = W.random_params(rng, c, 2)
+        obs = [W.random_pauli_sum(rng, n, 3)]
+        w = rng.standard_normal((2, 1))
+        a = oracle.grad_param_shift(c, params, data, obs, w, 2)
+        b = oracle.grad_fd(c, params, data, obs, w, 2)
+        _close(a[0], b[0], 2e-8, "shift vs FD params n=%d" % n)
+        _close(a[1], b[1], 2e-8, "shift vs FD data n=%d" % n)
+    # one controlled rotation: the two-term rule alone is not its derivative
+    c = W.Circuit(2, [W.Gate("h", (0,)), W.Gate("ry", (1,), "param", 1), W.Gate("crx", (0, 1), "param", 0)], 2)
+    th = np.array([0.9, 0.4])
+    obs = [[(1.0, "XI"), (0.5, "IZ")]]        # X on the control sees both branches
+    fd = oracle.grad_fd(c, th, None, obs, np.ones((1, 1)), 1)[0][0]
+    e = lambda t: oracle.forward(c, np.array([t, 0.4]), None, obs, 1)[0, 0]
+    two = (e(0.9 + np.pi / 2) - e(0.9 - np.pi / 2)) / 2
+    assert abs(two - fd) > 1e-3, "two-term rule matched a controlled rotation"
+    _close(oracle.grad_param_shift(c, th, None, obs, np.ones((1, 1)), 1)[0][0], fd, 2e-8, "four-term CRX")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -13,6 +13,14 @@ import oracle_pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "dq_oracle.c")
 
+# the controlled rotations' matrix: identity block, then the rotation block
+CR_BLOCK = """        U[0 * 4 + 0] = 1.0;
+        U[1 * 4 + 1] = 1.0;
+        U[2 * 4 + 2] = R[0] + I * R[1];
+        U[2 * 4 + 3] = R[2] + I * R[3];
+        U[3 * 4 + 2] = R[4] + I * R[5];
+        U[3 * 4 + 3] = R[6] + I * R[7];"""
+
 # (name, exact text in dq_oracle.c, replacement)
 MUTANTS = [
     ("ry-sign", "U[0] = c; U[1] = -s; U[2] = s; U[3] = c;", "U[0] = c; U[1] = s; U[2] = -s; U[3] = c;"),
@@ -39,6 +47,17 @@ MUTANTS = [
      "U[0 * 4 + 3] = I * s; U[1 * 4 + 2] = I * s; U[2 * 4 + 1] = I * s; U[3 * 4 + 0] = I * s;"),
     ("ryy-as-rxx", "U[0 * 4 + 3] = I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = I * s;",
      "U[0 * 4 + 3] = -I * s; U[1 * 4 + 2] = -I * s; U[2 * 4 + 1] = -I * s; U[3 * 4 + 0] = -I * s;"),
+    ("u3-phi-lambda-swapped", ["U[1] = -cexp(I * lambda) * sh;", "U[2] = cexp(I * phi) * sh;"],
+     ["U[1] = -cexp(I * phi) * sh;", "U[2] = cexp(I * lambda) * sh;"]),
+    ("u3-dropped-phase", "U[3] = cexp(I * (phi + lambda)) * ch;", "U[3] = ch;"),
+    ("u3-half-angle-dropped", "double ch = cos(theta / 2.0);", "double ch = cos(theta);"),
+    ("cr-block-transposed", ["U[2 * 4 + 3] = R[2] + I * R[3];", "U[3 * 4 + 2] = R[4] + I * R[5];"],
+     ["U[2 * 4 + 3] = R[4] + I * R[5];", "U[3 * 4 + 2] = R[2] + I * R[3];"]),
+    ("crx-as-cry", "op == ORC_CRX ? ORC_RX", "op == ORC_CRX ? ORC_RY"),
+    ("cr-control-on-zero", CR_BLOCK, CR_BLOCK.replace("U[0 * 4 + 0] = 1.0;", "U[3 * 4 + 3] = 1.0;")
+     .replace("U[1 * 4 + 1] = 1.0;", "U[2 * 4 + 2] = 1.0;").replace("U[2 * 4 + 2] = R", "U[0 * 4 + 0] = R")
+     .replace("U[2 * 4 + 3] = R", "U[0 * 4 + 1] = R").replace("U[3 * 4 + 2] = R", "U[1 * 4 + 0] = R")
+     .replace("U[3 * 4 + 3] = R", "U[1 * 4 + 1] = R")),
 ]
 
 
@@ -74,7 +93,7 @@ sys.path.insert(0, os.getcwd())
 import oracle, oracle_pins
 real = oracle.lib()
 L = ctypes.CDLL(sys.argv[1])
-for fn in ("orc_gate_matrix", "orc_apply", "orc_run", "orc_pauli_expval", "orc_prob_zero"):
+for fn in ("orc_gate_matrix", "orc_u3_matrix", "orc_apply", "orc_run", "orc_pauli_expval", "orc_prob_zero"):
     getattr(L, fn).argtypes = getattr(real, fn).argtypes
     getattr(L, fn).restype = getattr(real, fn).restype
 oracle._lib = L
@@ -97,6 +116,12 @@ PY_MUTANTS = [
     ("sample-le", "sample", "if x < c:", "if x <= c:", ["pin_sampling"]),
     ("sample-no-fallback", "sample", "out.append(res if res >= 0 else (last if last >= 0 else 0))",
      "out.append(res if res >= 0 else 0)", ["pin_sampling"]),
+    ("four-term-sign", "grad_param_shift", "return _D_PLUS * a - _D_MINUS * c", "return _D_PLUS * a + _D_MINUS * c",
+     ["pin_four_term_shift_equals_fd"]),
+    ("four-term-as-two-term", "grad_param_shift", "if circuit.gates[i].op in FOUR_TERM_GATES:",
+     "if False:", ["pin_four_term_shift_equals_fd"]),
+    ("u3-angle-not-chained", "grad_param_shift", "gp[g.idx + k] += g.scale * v", "gp[g.idx] += g.scale * v",
+     ["pin_four_term_shift_equals_fd"]),
 ]
 
 

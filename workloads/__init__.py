@@ -34,11 +34,21 @@ TWO_QUBIT_ROT = ("cp", "rzz")
 # the other two-qubit rotations (exp(-i t X(x)X / 2), exp(-i t Y(x)Y / 2)); not in
 # ALL_OPS, so that the seeded random circuits of the other tests stay as they are
 TWO_QUBIT_ROT_XY = ("rxx", "ryy")
+# the general one-qubit gate U3(theta, phi, lambda) (three consecutive angle
+# entries idx, idx+1, idx+2) and the controlled rotations (control, target);
+# likewise outside ALL_OPS
+ONE_QUBIT_U3 = ("u3",)
+CONTROLLED_ROT = ("crx", "cry", "crz")
 ALL_OPS = ONE_QUBIT_FIXED + ONE_QUBIT_ROT + TWO_QUBIT_FIXED + TWO_QUBIT_ROT + ("unitary",)
-KNOWN_OPS = ALL_OPS + TWO_QUBIT_ROT_XY
-ROTATIONS = ONE_QUBIT_ROT + TWO_QUBIT_ROT + TWO_QUBIT_ROT_XY
-ARITY = {**{o: 1 for o in ONE_QUBIT_FIXED + ONE_QUBIT_ROT},
-         **{o: 2 for o in TWO_QUBIT_FIXED + TWO_QUBIT_ROT + TWO_QUBIT_ROT_XY}}
+KNOWN_OPS = ALL_OPS + TWO_QUBIT_ROT_XY + ONE_QUBIT_U3 + CONTROLLED_ROT
+ROTATIONS = ONE_QUBIT_ROT + TWO_QUBIT_ROT + TWO_QUBIT_ROT_XY + ONE_QUBIT_U3 + CONTROLLED_ROT
+ARITY = {**{o: 1 for o in ONE_QUBIT_FIXED + ONE_QUBIT_ROT + ONE_QUBIT_U3},
+         **{o: 2 for o in TWO_QUBIT_FIXED + TWO_QUBIT_ROT + TWO_QUBIT_ROT_XY + CONTROLLED_ROT}}
+
+
+def n_angles(op: str) -> int:
+    """Angle entries a gate reads: U3 takes theta, phi, lambda."""
+    return 3 if op == "u3" else 1
 
 
 @dataclass(frozen=True)
@@ -69,9 +79,9 @@ class Circuit:
                 assert g.nq == ARITY[g.op], g
             assert len(set(g.wires)) == g.nq and all(0 <= w < self.n for w in g.wires), g
             if g.src == "param":
-                assert 0 <= g.idx < self.n_params, g
+                assert 0 <= g.idx and g.idx + n_angles(g.op) <= self.n_params, g
             elif g.src == "data":
-                assert 0 <= g.idx < self.n_data, g
+                assert 0 <= g.idx and g.idx + n_angles(g.op) <= self.n_data, g
 
 
 Term = Tuple[float, str]
@@ -252,12 +262,13 @@ def random_circuit(rng, n: int, ngates: int, ops: Sequence[str] = ALL_OPS,
             continue
         wires = tuple(int(w) for w in rng.choice(n, size=a, replace=False))
         if op in ROTATIONS:
+            k = n_angles(op)
             if with_data and rng.random() < 0.3:
                 gates.append(Gate(op, wires, "data", D, float(rng.choice([1.0, -0.5, 2.0]))))
-                D += 1
+                D += k
             else:
                 gates.append(Gate(op, wires, "param", P))
-                P += 1
+                P += k
         else:
             gates.append(Gate(op, wires))
     return Circuit(n, gates, P, D)
@@ -293,6 +304,68 @@ def dist_listing():
     g = [Gate("ry", (q,), "data", q) for q in range(4)] + cnot_ring(4)
     c = Circuit(4, g, 0, 4)
     return c, np.zeros(0), np.arange(4, dtype=float)[None, :], [[(1.0, "ZIII")], [(1.0, "IXII")]]
+
+
+def qresnet(residual: bool = True):
+    """The curve-fitting model of the QResNet listing ("code:qresnet",
+    section 4.3).  Residual form on two wires: RY(theta) on wire 0, U3 on
+    wire 1, the data encoded as an RY on wire 1 controlled by wire 0, RY on
+    wire 0, U3 on wire 1; observables Z1 and Z0 Z1.  Plain form on one wire:
+    U3, RY(data), U3; observable Z0.  Parameters in gate order (U3 takes
+    three); one data column.  Returns (circuit, observables)."""
+    if residual:
+        g = [Gate("ry", (0,), "param", 0), Gate("u3", (1,), "param", 1), Gate("cry", (0, 1), "data", 0),
+             Gate("ry", (0,), "param", 4), Gate("u3", (1,), "param", 5)]
+        return Circuit(2, g, 8, 1), [[(1.0, "IZ")], [(1.0, "ZZ")]]
+    g = [Gate("u3", (0,), "param", 0), Gate("ry", (0,), "data", 0), Gate("u3", (0,), "param", 3)]
+    return Circuit(1, g, 6, 1), [[(1.0, "Z")]]
+
+
+def qcnn(n: int = 12):
+    """The QCNN of its listing ("code:qcnn_demo", section 4.3) on n = 12
+    wires: data encoded by RY on all 12 wires, a convolution (RXX then RYY
+    on pairs (i, i+1), i even), pooling (CRY with control 2i+1 and target
+    2i); RY encoding on wires 0..5, convolution and pooling on 6 wires; RY
+    encoding on wires 0..2, RXX and RYY on (0,1) and (1,2), then CRY(1, 0)
+    and CRY(2, 0).  21 data columns (12 + 6 + 3), parameters in gate order;
+    observable Z on wire 0.  Returns (circuit, observables)."""
+    assert n == 12, "the listing's layer sizes are those of 12 wires"
+    g: List[Gate] = []
+    P = D = 0
+
+    def enc(wires):
+        nonlocal D
+        for q in wires:
+            g.append(Gate("ry", (q,), "data", D))
+            D += 1
+
+    def rot(op, wires):
+        nonlocal P
+        g.append(Gate(op, wires, "param", P))
+        P += 1
+
+    def conv(m):
+        for i in range(0, m - 1, 2):
+            rot("rxx", (i, i + 1))
+            rot("ryy", (i, i + 1))
+
+    def pool(m):
+        for i in range(m // 2):
+            rot("cry", (2 * i + 1, 2 * i))
+
+    enc(range(12))
+    conv(12)
+    pool(12)
+    enc(range(6))
+    conv(6)
+    pool(6)
+    enc(range(3))
+    for i in range(2):
+        rot("rxx", (i, i + 1))
+        rot("ryy", (i, i + 1))
+    rot("cry", (1, 0))
+    rot("cry", (2, 0))
+    return Circuit(n, g, P, D), [[(1.0, z_string(n, [0], "Z"))]]
 
 
 def qft(n: int, reverse: bool = False) -> Circuit:

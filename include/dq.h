@@ -84,7 +84,16 @@ typedef enum {
     DQ_OP_CP = 10, DQ_OP_RZZ = 11,
     DQ_OP_UNITARY = 12,         /* dense 2^nq x 2^nq matrix, nq = 1..5 */
     DQ_OP_RXX = 13,             /* exp(-i t X(x)X / 2) and exp(-i t Y(x)Y / 2): the two-qubit */
-    DQ_OP_RYY = 14              /* rotations of the paper's gate set beside RZZ (section 4) */
+    DQ_OP_RYY = 14,             /* rotations of the paper's gate set beside RZZ (section 4) */
+    DQ_OP_U3 = 15,              /* U3(theta, phi, lambda) = [[cos(theta/2), -e^{i lambda} sin(theta/2)],
+                                   [e^{i phi} sin(theta/2), e^{i(phi+lambda)} cos(theta/2)]], the
+                                   general one-qubit gate of the paper's QResNet (section 4.3); its
+                                   three angles are scale * source[idx + k], k = 0, 1, 2 (scale for
+                                   each when the source is DQ_SRC_NONE) */
+    DQ_OP_CRX = 16,             /* controlled rotations on (control, target): the identity where */
+    DQ_OP_CRY = 17,             /* the control is 0, RX / RY / RZ(t) where it is 1 (the pooling  */
+    DQ_OP_CRZ = 18              /* gate of the QCNN and the controlled encoding of the QResNet,
+                                   section 4.3) */
 } dq_op;
 
 typedef enum { DQ_SRC_NONE = 0, DQ_SRC_PARAM = 1, DQ_SRC_DATA = 2 } dq_src;
@@ -263,6 +272,31 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch,
                           int64_t data_bstride, const double *grad_out, double *grad_params,
                           double *grad_data, int32_t preserve_state, void *ws, size_t ws_bytes,
                           void *stream);
+
+/* Hessian (paper 3.1, the second-order gradient benchmark) of
+ * L = sum_o weights[o] E_o for one sample with shared parameters:
+ * hess[p][q] = d^2 L / dparams[p] dparams[q], row-major [P][P] float64,
+ * overwritten.  params: device [P]; data: device [D] (one sample's row;
+ * NULL when the circuit reads no data; data angles are held fixed);
+ * weights: device [nobs] float64.  Method: every gate angle that reads a
+ * parameter ("occurrence", K of them: U3 has three, a controlled rotation
+ * two, other rotations one) is shifted by +pi/2 and -pi/2 in a batch of 2K
+ * circuits; one batched forward and adjoint sweep gives the gradient with
+ * respect to every occurrence angle of each shifted circuit, and
+ * H_ab = (g_a(+b) - g_a(-b)) / 2 is exact for the planned gates (the
+ * two-term shift rule of generators with eigenvalues a distance 1 apart);
+ * H[p][q] sums H_ab times both chain factors (scales) over the
+ * occurrences of p and q.  max_shifts: occurrences per batch (0 = all K;
+ * fewer bound the workspace at 2 * max_shifts states); batches run in
+ * order and the result is deterministic.  ws: caller-owned device buffer of
+ * at least dq_hessian_workspace_size bytes.  The first call builds a
+ * derived plan (host) that the plan keeps until dq_plan_destroy.
+ * Errors: DQ_ERR_INVALID_ARG (NULL pointer, a plan without parameters, a
+ * negative max_shifts), DQ_ERR_OUT_OF_RANGE (2 * max_shifts states beyond
+ * the batch or memory limit), DQ_ERR_WORKSPACE; nothing is enqueued then. */
+dq_status dq_hessian_workspace_size(dq_plan plan, dq_obs obs, int32_t max_shifts, size_t *bytes);
+dq_status dq_hessian(dq_plan plan, dq_obs obs, const double *params, const double *data, const double *weights,
+                     double *hess, int32_t max_shifts, void *ws, size_t ws_bytes, void *stream);
 
 /* Kernel timing for benchmarks.  While enabled on a plan, every kernel
  * launch made for it (apply, expval, adjoint) is bracketed by a pair of

@@ -313,6 +313,70 @@ def grad_param_shift(circuit, params, data, observables, weights, batch: int,
     return gp, gd
 
 
+def _shift_rule(op: str):
+    """(coefficients, shifts) of a gate angle's derivative rule,
+    dE/dt = sum_i c_i E(t + s_i): two-term for generators with two
+    eigenvalues a distance 1 apart, four-term for the controlled rotations."""
+    if op in FOUR_TERM_GATES:
+        return ((_D_PLUS, -_D_PLUS, -_D_MINUS, _D_MINUS),
+                (np.pi / 2, -np.pi / 2, 3 * np.pi / 2, -3 * np.pi / 2))
+    if op in SHIFT_RULE_GATES:
+        return ((0.5, -0.5), (np.pi / 2, -np.pi / 2))
+    raise ValueError("no shift rule for %s" % op)
+
+
+def hessian_param_shift(circuit, params, data, observables, weights, threads: Optional[int] = None):
+    """Hessian d^2 L / dtheta_p dtheta_q of L = sum_o w[o] E_o for one
+    sample with shared parameters params[P] (data: one row or None) -- the
+    second-order benchmark of paper section 3.1.  Each gate-angle occurrence
+    a (gate i, angle k, reading params[idx + k] with chain factor scale) has
+    the derivative rule D_a of its gate; D_a D_b L is that rule applied
+    along angle a to the function that the rule along b gives,
+        D_a D_b L = sum_i sum_j c_i c_j L(angles + s_i e_a + s_j e_b),
+    (for a = b both shifts land on the same angle).  This is exact: E, and
+    its derivative along b, are trigonometric polynomials in angle a with
+    the frequencies of a's generator, for which D_a is exact.  Chained
+    through theta = scale * source:
+        H[p, q] = sum_{a reads p} sum_{b reads q} scale_a scale_b D_a D_b L.
+    Returns H [P, P] (float64)."""
+    enc = _Encoded(circuit)
+    w = np.asarray(weights, float).reshape(len(observables))
+    p = np.asarray(params, float).reshape(-1)
+    dat = None if data is None else np.asarray(data, float).reshape(1, -1)
+    occ = [(i, k) for i, g in enumerate(circuit.gates) if g.src == "param" for k in range(n_angles(g.op))]
+    th0 = enc.angles(p, dat, 0)
+
+    def L_at(th):
+        return float(np.dot(w, expvals(circuit.n, _run_angles(enc, th), observables)))
+
+    def one(pair):
+        a, b = pair
+        (ia, ka), (ib, kb) = occ[a], occ[b]
+        ca, sa = _shift_rule(circuit.gates[ia].op)
+        cb, sb = _shift_rule(circuit.gates[ib].op)
+        v = 0.0
+        for ci, si in zip(ca, sa):
+            for cj, sj in zip(cb, sb):
+                th = th0.copy()
+                th[ia, ka] += si
+                th[ib, kb] += sj
+                v += ci * cj * L_at(th)
+        return v
+
+    pairs = [(a, b) for a in range(len(occ)) for b in range(a, len(occ))]
+    with _pool(threads) as ex:
+        vals = list(ex.map(one, pairs))
+    H = np.zeros((len(p), len(p)))
+    for (a, b), v in zip(pairs, vals):
+        ga, gb = circuit.gates[occ[a][0]], circuit.gates[occ[b][0]]
+        pa, pb = ga.idx + occ[a][1], gb.idx + occ[b][1]
+        f = ga.scale * gb.scale * v
+        H[pa, pb] += f
+        if a != b:               # D_a D_b = D_b D_a: the mirrored pair
+            H[pb, pa] += f
+    return H
+
+
 def grad_fd(circuit, params, data, observables, weights, batch: int, h: float = 1e-6,
             threads: Optional[int] = None, samples: Optional[Sequence[int]] = None,
             param_subset: Optional[Sequence[int]] = None, with_data: bool = True):

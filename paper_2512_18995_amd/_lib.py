@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdq.so")
 
 OPS = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "cnot": 7, "cz": 8, "swap": 9,
-       "cp": 10, "rzz": 11, "unitary": 12, "rxx": 13, "ryy": 14}
+       "cp": 10, "rzz": 11, "unitary": 12, "rxx": 13, "ryy": 14, "u3": 15, "crx": 16, "cry": 17,
+       "crz": 18}
 SRC = {"none": 0, "param": 1, "data": 2}
 STATUS = {0: "DQ_OK", 1: "DQ_ERR_INVALID_ARG", 2: "DQ_ERR_UNSUPPORTED", 3: "DQ_ERR_WORKSPACE",
           4: "DQ_ERR_OUT_OF_RANGE", 5: "DQ_ERR_HIP", 6: "DQ_ERR_INTERNAL"}
@@ -25,7 +26,8 @@ EXPORTS = ["dq_plan_create", "dq_plan_destroy", "dq_plan_get_stats", "dq_obs_cre
            "dq_last_error", "dq_version", "dq_profile_enable", "dq_profile_read",
            "dq_multi_create", "dq_multi_destroy", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
            "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe",
-           "dq_plan_jit_source", "dq_probs_workspace_size", "dq_probs", "dq_sample"]
+           "dq_plan_jit_source", "dq_probs_workspace_size", "dq_probs", "dq_sample",
+           "dq_hessian_workspace_size", "dq_hessian"]
 PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other", "dense"]
 
 
@@ -102,13 +104,15 @@ def lib():
         L.dq_probs_workspace_size.argtypes = [vp, c_int64, c_int32, POINTER(c_size_t)]
         L.dq_probs.argtypes = [vp, vp, c_int64, POINTER(c_int32), c_int32, vp, vp, c_size_t, vp]
         L.dq_sample.argtypes = [vp, c_int64, c_int32, vp, c_int32, vp, vp]
+        L.dq_hessian_workspace_size.argtypes = [vp, vp, c_int32, POINTER(c_size_t)]
+        L.dq_hessian.argtypes = [vp, vp, vp, vp, vp, vp, c_int32, vp, c_size_t, vp]
         L.dq_last_error.restype = c_char_p
         L.dq_version.restype = c_int32
         for f in ("dq_plan_create", "dq_plan_get_stats", "dq_obs_create", "dq_workspace_size", "dq_state_init",
                   "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read",
                   "dq_multi_create", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
                   "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe", "dq_plan_jit_source",
-                  "dq_probs_workspace_size", "dq_probs", "dq_sample"):
+                  "dq_probs_workspace_size", "dq_probs", "dq_sample", "dq_hessian_workspace_size", "dq_hessian"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib

@@ -16,7 +16,10 @@ namespace dq {
 enum : int32_t {
     OP_H = 0, OP_X, OP_Y, OP_Z, OP_RX, OP_RY, OP_RZ, OP_CNOT, OP_CZ, OP_SWAP, OP_CP, OP_RZZ,
     OP_UNITARY,
-    OP_RXX, OP_RYY   // plan input only: expanded into basis changes around an RZZ
+    OP_RXX, OP_RYY,  // plan input only: expanded into basis changes around an RZZ
+    OP_U3,           // plan input only: phase(lambda), RY(theta), phase(phi)
+    OP_CRX, OP_CRY, OP_CRZ,   // plan input only: two half-angle rotations around two CNOT / CZ
+    OP_PHASE = 32    // internal: diag(1, e^{i t}) = e^{i t/2} RZ(t); the angle of U3's phi and lambda
 };
 enum : int32_t { SRC_NONE = 0, SRC_PARAM = 1, SRC_DATA = 2 };
 
@@ -158,6 +161,15 @@ hipError_t launch_grad_gate(int dbl, const void *psi, const void *lam, int32_t n
 hipError_t launch_grad_final(const double *partial, int64_t batch, int32_t wps, int32_t ngrad,
                              const int64_t *csr_off, const int32_t *csr_g, const double *csr_f,
                              int64_t nout, int32_t per_sample, double *out, hipStream_t s);
+// Hessian by shifted adjoints (kernels.hip): angle rows of 2 mc shifted
+// circuits, the observable weights broadcast to every row, and the
+// deterministic accumulation of H[P][P] from the rows' gradients (the first
+// chunk, c0 = 0, overwrites H)
+hipError_t launch_hess_rows(const double *params, const int32_t *occ_param, const double *occ_scale, int64_t K,
+                            int64_t c0, int64_t mc, double *rows, hipStream_t s);
+hipError_t launch_bcast_rows(const double *w, int32_t nobs, int64_t rows, double *out, hipStream_t s);
+hipError_t launch_hess_accum(const double *G, int64_t K, int64_t c0, int64_t mc, const int64_t *poff,
+                             const int32_t *pocc, const double *occ_scale, int64_t P, double *H, hipStream_t s);
 // observables at most the diagonal expectation kernel sums at once
 constexpr int ZD_MAXOBS = 8;
 // blocks of the diagonal expectation kernel per sample (4 waves of

@@ -53,6 +53,12 @@ __device__ void gate_matrix(const DGate &g, double th, const double2 *fixed, dou
     case OP_RX: U[0] = {c, 0}; U[1] = {0, -s}; U[2] = {0, -s}; U[3] = {c, 0}; break;
     case OP_RY: U[0] = {c, 0}; U[1] = {-s, 0}; U[2] = {s, 0}; U[3] = {c, 0}; break;
     case OP_RZ: U[0] = {c, -s}; U[3] = {c, s}; break;
+    case OP_PHASE: {
+        double sp, cp;
+        sincos(th, &sp, &cp);
+        U[0] = {1, 0}; U[3] = {cp, sp};
+        break;
+    }
     case OP_CNOT: U[0] = {1, 0}; U[5] = {1, 0}; U[11] = {1, 0}; U[14] = {1, 0}; break;
     case OP_CZ: U[0] = {1, 0}; U[5] = {1, 0}; U[10] = {1, 0}; U[15] = {-1, 0}; break;
     case OP_SWAP: U[0] = {1, 0}; U[6] = {1, 0}; U[9] = {1, 0}; U[15] = {1, 0}; break;
@@ -584,6 +590,53 @@ __global__ void k_grad_final(const double *partial, int64_t batch, int wps, int 
     out[i] = sum;
 }
 
+// ============================================================ Hessian
+// Angle rows of the shifted circuits: occurrence a (a gate angle that reads
+// parameter occ_param[a] with chain factor occ_scale[a]) gets angle
+// occ_scale[a] * params[occ_param[a]] in every row; rows 2r and 2r+1 shift
+// occurrence c0 + r by +pi/2 and -pi/2.
+__global__ void k_hess_rows(const double *params, const int32_t *occ_param, const double *occ_scale, int64_t K,
+                            int64_t c0, int64_t mc, double *rows) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 2 * mc * K) return;
+    const int64_t row = i / K, a = i % K;
+    double v = occ_scale[a] * params[occ_param[a]];
+    if (a == c0 + row / 2) v += (row & 1) ? -0.5 * M_PI : 0.5 * M_PI;
+    rows[i] = v;
+}
+
+// rows x nobs copies of the observable weights (the adjoint seed of every
+// shifted circuit)
+__global__ void k_bcast_rows(const double *w, int32_t nobs, int64_t rows, double *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < rows * nobs) out[i] = w[i % nobs];
+}
+
+// H[p][q] += sum over occurrences b of parameter q inside this chunk
+// [c0, c0+mc) of s_b sum over occurrences a of parameter p of
+// s_a (G[2(b-c0)][a] - G[2(b-c0)+1][a]) / 2, where G[row][a] is the
+// gradient of the shifted circuit `row` with respect to angle a.  One thread
+// per (p, q), sums in a fixed order: deterministic.
+__global__ void k_hess_accum(const double *G, int64_t K, int64_t c0, int64_t mc, const int64_t *poff,
+                             const int32_t *pocc, const double *occ_scale, int64_t P, double *H) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= P * P) return;
+    const int64_t p = i / P, q = i % P;
+    double acc = 0.0;
+    for (int64_t eb = poff[q]; eb < poff[q + 1]; ++eb) {
+        const int64_t b = pocc[eb];
+        if (b < c0 || b >= c0 + mc) continue;
+        const double *gp = G + 2 * (b - c0) * K, *gm = gp + K;
+        double s = 0.0;
+        for (int64_t ea = poff[p]; ea < poff[p + 1]; ++ea) {
+            const int64_t a = pocc[ea];
+            s += occ_scale[a] * 0.5 * (gp[a] - gm[a]);
+        }
+        acc += occ_scale[b] * s;
+    }
+    H[i] = (c0 == 0 ? 0.0 : H[i]) + acc;
+}
+
 constexpr int EXP_TM = 32;
 
 // Partial sums S_t = sum_j (-1)^{|j & z_t|} conj(psi_{j^x}) psi_j over this
@@ -1087,6 +1140,31 @@ hipError_t launch_grad_final(const double *partial, int64_t batch, int32_t wps, 
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, partial, batch, wps, ngrad,
                        csr_off, csr_g, csr_f, nout, per_sample, out);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_hess_rows(const double *params, const int32_t *occ_param, const double *occ_scale, int64_t K,
+                            int64_t c0, int64_t mc, double *rows, hipStream_t s) {
+    const int64_t total = 2 * mc * K;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hess_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, params, occ_param,
+                       occ_scale, K, c0, mc, rows);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_bcast_rows(const double *w, int32_t nobs, int64_t rows, double *out, hipStream_t s) {
+    const int64_t total = rows * nobs;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bcast_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, nobs, rows, out);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_hess_accum(const double *G, int64_t K, int64_t c0, int64_t mc, const int64_t *poff,
+                             const int32_t *pocc, const double *occ_scale, int64_t P, double *H, hipStream_t s) {
+    const int64_t total = P * P;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hess_accum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, K, c0, mc, poff,
+                       pocc, occ_scale, P, H);
     DQ_LAUNCH_RET;
 }
 

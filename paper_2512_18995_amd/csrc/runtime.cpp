@@ -69,21 +69,25 @@ dq_status fail_nothrow(const char *what) noexcept {
     } while (0)
 
 bool is_rotation(int op) {
-    return op == OP_RX || op == OP_RY || op == OP_RZ || op == OP_CP || op == OP_RZZ || op == OP_RXX || op == OP_RYY;
+    return op == OP_RX || op == OP_RY || op == OP_RZ || op == OP_CP || op == OP_RZZ || op == OP_RXX || op == OP_RYY ||
+           op == OP_U3 || op == OP_CRX || op == OP_CRY || op == OP_CRZ || op == OP_PHASE;
 }
 int arity(int op) {
     switch (op) {
-    case OP_CNOT: case OP_CZ: case OP_SWAP: case OP_CP: case OP_RZZ: case OP_RXX: case OP_RYY: return 2;
+    case OP_CNOT: case OP_CZ: case OP_SWAP: case OP_CP: case OP_RZZ: case OP_RXX: case OP_RYY:
+    case OP_CRX: case OP_CRY: case OP_CRZ: return 2;
     case OP_UNITARY: return -1;
     default: return 1;
     }
 }
-bool is_diag1(int op) { return op == OP_RZ || op == OP_Z; }
+bool is_diag1(int op) { return op == OP_RZ || op == OP_Z || op == OP_PHASE; }
 int gen_of(int op) {
     switch (op) {
     case OP_RX: return GEN_X;
     case OP_RY: return GEN_Y;
-    case OP_RZ: return GEN_Z;
+    // diag(1, e^{it}) = e^{it/2} RZ(t): dE/dt = Im<l|Z|p> - Im<l|p>, and <l|p> =
+    // sum_o w_o <psi|H_o|psi> is real, so the phase gate takes RZ's generator
+    case OP_RZ: case OP_PHASE: return GEN_Z;
     case OP_RZZ: return GEN_ZZ;
     case OP_CP: return GEN_P11;
     default: return GEN_NONE;
@@ -168,6 +172,9 @@ struct DevData {
     int64_t *poff = nullptr, *doff = nullptr;
     int32_t *pg = nullptr, *dg = nullptr;
     double *pf = nullptr, *df = nullptr;
+    int32_t *occ_param = nullptr, *hocc = nullptr;   // Hessian: angle occurrences of parameters
+    double *occ_scale = nullptr;
+    int64_t *hoff = nullptr;
 };
 
 }  // namespace
@@ -198,6 +205,17 @@ struct dq_plan_s {
     std::vector<int64_t> poff, doff;
     std::vector<int32_t> pg, dg;
     std::vector<double> pf, df;
+    // Hessian (dq_hessian): the expanded gate list in canonical bit order,
+    // the gate angles that read a parameter ("occurrences", in gate order:
+    // parameter index and chain factor), parameter -> occurrences (CSR), and
+    // the derived plan in which occurrence k reads its own parameter k with
+    // scale 1, built on the first dq_hessian call
+    std::vector<DGate> canon;
+    std::vector<int32_t> occ_param, hocc;
+    std::vector<double> occ_scale;
+    std::vector<int64_t> hoff;
+    std::mutex hmu;
+    std::unique_ptr<dq_plan_s> hess;
     std::mutex mu;
     std::map<int, DevData> dev;
     // kernel timing (dq_profile_enable / dq_profile_read)
@@ -970,6 +988,11 @@ dq_plan_s *plan_clone_base(const dq_plan_s &p) {
     q->fixed = p.fixed;
     q->user_gates = p.user_gates;
     q->entry_gates = 0;
+    q->canon = p.canon;
+    q->occ_param = p.occ_param;
+    q->occ_scale = p.occ_scale;
+    q->hoff = p.hoff;
+    q->hocc = p.hocc;
     return q;
 }
 
@@ -1043,7 +1066,9 @@ dq_status ensure_device(dq_plan_s &p, DevData **out) {
     const size_t o_g = put(blob, p.gates), o_f = put(blob, p.fixed), o_s = put(blob, p.slots),
                  o_o = put(blob, p.ops), o_l = put(blob, p.lsg), o_fo = put(blob, p.fold_off),
                  o_po = put(blob, p.poff), o_pg = put(blob, p.pg), o_pf = put(blob, p.pf),
-                 o_do = put(blob, p.doff), o_dg = put(blob, p.dg), o_df = put(blob, p.df);
+                 o_do = put(blob, p.doff), o_dg = put(blob, p.dg), o_df = put(blob, p.df),
+                 o_op = put(blob, p.occ_param), o_os = put(blob, p.occ_scale), o_ho = put(blob, p.hoff),
+                 o_hc = put(blob, p.hocc);
     void *d = nullptr;
     DQ_HIP(hipMalloc(&d, blob.size()));
     hipError_t e = hipMemcpy(d, blob.data(), blob.size(), hipMemcpyHostToDevice);
@@ -1068,6 +1093,10 @@ dq_status ensure_device(dq_plan_s &p, DevData **out) {
     dd.doff = (int64_t *)(b + o_do);
     dd.dg = (int32_t *)(b + o_dg);
     dd.df = (double *)(b + o_df);
+    dd.occ_param = (int32_t *)(b + o_op);
+    dd.occ_scale = (double *)(b + o_os);
+    dd.hoff = (int64_t *)(b + o_ho);
+    dd.hocc = (int32_t *)(b + o_hc);
     if (!p.jnames.empty()) {
         std::string err;
         if (!jit_load(p.jnames, p.jsrcs, dd.jfn, err)) {
@@ -1305,6 +1334,135 @@ dq_status apply_on_device(dq_plan_s &p, DevData &d, void *state, int64_t batch, 
     return run_program(p, d, prog, state, nullptr, batch, mats, mstride, nullptr, 0, s, timed);
 }
 
+// The adjoint sweep of dq_adjoint_grad on a validated call (workspace laid
+// out by L at w): seed lambda = sum_o w_o H_o psi, un-apply every gate from
+// psi and lambda while summing the gradient terms, then reduce them in a
+// fixed order into grad_params / grad_data.
+dq_status adjoint_core(dq_plan_s &plan, DevData &d, const dq_obs_s &obs, const DGroup *g, const DTerm *t, void *state,
+                       int64_t batch, const double *params, int64_t params_bstride, const double *data,
+                       int64_t data_bstride, const double *grad_out, double *grad_params, double *grad_data,
+                       int32_t preserve_state, char *w, const WsLayout &L, hipStream_t s) {
+    const int per_sample = (params_bstride != 0 || data_bstride != 0) ? 1 : 0;
+    void *mats = w + L.mats;
+    void *lam = w + L.lam;
+    double *partial = (double *)(w + L.part);
+    const int64_t bm = per_sample ? batch : 1;
+    const int64_t mstride = per_sample ? plan.block : 0;
+    // partial sums per sample: at most grad_waves (the workspace size), and
+    // no more than the adjoint tile kernel keeps resident, so that one
+    // round of waves covers every tile
+    int wps = (int)grad_waves(plan, batch);
+    if (plan.R_adj > 0) {
+        const int resident = d.jit_adj_cap > 0 ? d.jit_adj_cap : tile_adj_capacity(plan.dbl, plan.R_adj);
+        const int cap = std::max<int64_t>(1, resident / batch);
+        wps = std::min(wps, cap);
+    }
+    void *psi = state;
+    hipError_t e;
+    const double SB = state_bytes(plan, batch);
+    if (preserve_state) {
+        psi = w + L.keep;
+        ProfScope pc(plan, DQ_PROF_OTHER, 1, 2 * SB, s);
+        e = launch_copy(plan.dbl, psi, state, batch << plan.n, s);
+        pc.done();
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "copy: %s", hipGetErrorString(e));
+    }
+    ProfScope pp(plan, DQ_PROF_OTHER, 1, 0.0, s);
+    e = launch_prepare(plan.dbl, d.gates, d.fixed, d.slots + plan.adj.slot_lo,
+                       (int32_t)(plan.adj.slot_hi - plan.adj.slot_lo), params, params_bstride, data, data_bstride,
+                       mats, plan.block, bm, s);
+    pp.done();
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
+    int32_t dt0, dt1;
+    zdiag_range(plan, obs, dt0, dt1);
+    ProfScope pl(plan, DQ_PROF_LAMBDA, 1, 2 * SB, s);
+    e = launch_lambda(plan.dbl, psi, lam, plan.n, batch, g, (int32_t)obs.groups.size(), t, grad_out, obs.nobs, dt0,
+                      dt1, s);
+    pl.done();
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "lambda: %s", hipGetErrorString(e));
+    dq_status st = run_program(plan, d, plan.adj, psi, lam, batch, mats, mstride, partial, wps, s);
+    if (st != DQ_OK) return st;
+    ProfScope pf(plan, DQ_PROF_OTHER, 1, 0.0, s);
+    if (plan.nparams > 0) {
+        e = launch_grad_final(partial, batch, wps, plan.ngrad, d.poff, d.pg, d.pf, plan.nparams,
+                              params_bstride != 0 ? 1 : 0, grad_params, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "grad reduce: %s", hipGetErrorString(e));
+    }
+    if (grad_data && plan.ndata > 0) {
+        e = launch_grad_final(partial, batch, wps, plan.ngrad, d.doff, d.dg, d.df, plan.ndata,
+                              data_bstride != 0 ? 1 : 0, grad_data, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "grad reduce: %s", hipGetErrorString(e));
+    }
+    pf.done();
+    return DQ_OK;
+}
+
+// ---------------------------------------------------------------- Hessian
+// The derived plan of dq_hessian: the same expanded gates, occurrence k
+// (the k-th gate angle that reads a parameter) reading parameter k with
+// scale 1, so that a batch row of angles can shift one occurrence alone and
+// the adjoint returns the gradient with respect to every occurrence's angle.
+dq_status ensure_hess_plan(dq_plan_s &p, dq_plan_s **out) {
+    std::lock_guard<std::mutex> lk(p.hmu);
+    if (!p.hess) {
+        std::unique_ptr<dq_plan_s> q(new dq_plan_s());
+        q->n = p.n;
+        q->dbl = p.dbl;
+        q->opt = p.opt;
+        q->nparams = (int64_t)p.occ_param.size();
+        q->ndata = p.ndata;
+        q->fixed = p.fixed;
+        q->gates = p.canon;
+        int64_t k = 0;
+        for (DGate &g : q->gates)
+            if (g.src == SRC_PARAM) {
+                g.idx = k++;
+                g.scale = 1.0;
+            }
+        q->user_gates = (int64_t)q->gates.size();
+        q->canon = q->gates;
+        dq_status st = build_plan(*q);
+        if (st != DQ_OK) return st;
+        if (q->opt.layout == 0) q.reset(search_layout(q.release()));
+        if (q->opt.jit) jit_generate(*q);
+        p.hess = std::move(q);
+    }
+    *out = p.hess.get();
+    return DQ_OK;
+}
+
+// occurrences shifted per batch: all (max_shifts = 0) or max_shifts, within
+// the batch limit (two shifted circuits per occurrence)
+dq_status hess_shifts(const dq_plan_s &p, int32_t max_shifts, int64_t &m) {
+    if (max_shifts < 0) return fail(DQ_ERR_INVALID_ARG, "max_shifts %d is negative", max_shifts);
+    const int64_t K = std::max<int64_t>((int64_t)p.occ_param.size(), 1);
+    m = max_shifts == 0 ? K : std::min<int64_t>(max_shifts, K);
+    if (2 * m > 65535) return fail(DQ_ERR_OUT_OF_RANGE, "%lld shifts per batch exceed 32767", (long long)m);
+    return check_batch(p, 2 * m);
+}
+
+struct HessLayout {
+    size_t rows = 0, grads = 0, wts = 0, states = 0, sub = 0, total = 0;
+};
+
+HessLayout hess_layout(const dq_plan_s &p, const dq_plan_s &h, const dq_obs_s *o, int64_t m) {
+    HessLayout L;
+    const int64_t K = std::max<int64_t>((int64_t)p.occ_param.size(), 1), B = 2 * m;
+    size_t off = 0;
+    L.rows = off;
+    off = align256(off + (size_t)(B * K) * 8);
+    L.grads = off;
+    off = align256(off + (size_t)(B * K) * 8);
+    L.wts = off;
+    off = align256(off + (size_t)(B * std::max(o->nobs, 1)) * 8);
+    L.states = off;
+    off = align256(off + (size_t)B * ((size_t)1 << p.n) * (p.dbl ? 16 : 8));
+    L.sub = off;
+    off += layout(h, o, B, 1, 1).total;
+    L.total = off;
+    return L;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -1341,7 +1499,7 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     p->ndata = ndata;
     for (int64_t g = 0; g < ngates; ++g) {
         const dq_gate &G = gates[g];
-        if (G.op < DQ_OP_H || G.op > DQ_OP_RYY) {
+        if (G.op < DQ_OP_H || G.op > DQ_OP_CRZ) {
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: unknown op %d", (long long)g, G.op);
         }
         const int a = arity(G.op);
@@ -1363,8 +1521,9 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
         if (G.src != DQ_SRC_NONE && !is_rotation(G.op)) {
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: op %d takes no angle", (long long)g, G.op);
         }
-        if ((G.src == DQ_SRC_PARAM && (G.idx < 0 || G.idx >= nparams)) ||
-            (G.src == DQ_SRC_DATA && (G.idx < 0 || G.idx >= ndata))) {
+        const int64_t nang = G.op == DQ_OP_U3 ? 3 : 1;   // U3 reads idx, idx+1, idx+2
+        if ((G.src == DQ_SRC_PARAM && (G.idx < 0 || G.idx > nparams - nang)) ||
+            (G.src == DQ_SRC_DATA && (G.idx < 0 || G.idx > ndata - nang))) {
             return fail(DQ_ERR_INVALID_ARG, "gate %lld: source index %lld out of range", (long long)g, (long long)G.idx);
         }
         if (!std::isfinite(G.scale)) {
@@ -1401,6 +1560,48 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
             basis(-1.0);
             continue;
         }
+        if (G.op == DQ_OP_U3) {
+            // U3(theta, phi, lambda) = P(phi) RY(theta) P(lambda) with the phase
+            // gate P(t) = diag(1, e^{it}): the product's entries are those of U3
+            // exactly (no global phase), and each factor carries one angle and
+            // its gradient slot (theta at idx, phi at idx+1, lambda at idx+2)
+            const int64_t k_of[3] = {2, 0, 1};
+            const int op_of[3] = {OP_PHASE, OP_RY, OP_PHASE};
+            for (int i = 0; i < 3; ++i) {
+                DGate F = D;
+                F.op = op_of[i];
+                F.idx = G.src == DQ_SRC_NONE ? G.idx : G.idx + k_of[i];
+                p->gates.push_back(F);
+            }
+            continue;
+        }
+        if (G.op == DQ_OP_CRX || G.op == DQ_OP_CRY || G.op == DQ_OP_CRZ) {
+            // controlled R(t) on (c, t) = E R(-t/2) E R(t/2) with E = CNOT(c, t)
+            // for RY and RZ (X R(a) X = R(-a)) and E = CZ(c, t) for RX
+            // (Z RX(a) Z = RX(-a)): where the control is 0 the two halves
+            // cancel, where it is 1 they add.  Both halves read the gate's
+            // angle source with half its scale, so its gradient is the sum of
+            // theirs (chain factors +1/2 and -1/2)
+            const int rop = G.op == DQ_OP_CRX ? OP_RX : (G.op == DQ_OP_CRY ? OP_RY : OP_RZ);
+            DGate E{};
+            E.op = G.op == DQ_OP_CRX ? OP_CZ : OP_CNOT;
+            E.nq = 2;
+            E.bits[0] = D.bits[0];
+            E.bits[1] = D.bits[1];
+            E.src = SRC_NONE;
+            E.mat_off = -1;
+            for (int h = 0; h < 2; ++h) {
+                DGate R = D;
+                R.op = rop;
+                R.nq = 1;
+                R.bits[0] = D.bits[1];
+                R.bits[1] = 0;
+                R.scale = (h ? -0.5 : 0.5) * G.scale;
+                p->gates.push_back(R);
+                p->gates.push_back(E);
+            }
+            continue;
+        }
         if (G.op == DQ_OP_UNITARY) {
             if (!G.matrix) {
                 return fail(DQ_ERR_INVALID_ARG, "gate %lld: UNITARY without a matrix", (long long)g);
@@ -1412,6 +1613,21 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
         p->gates.push_back(D);
     }
     p->user_gates = (int64_t)p->gates.size();
+    p->canon = p->gates;
+    {
+        std::vector<std::vector<int32_t>> by_param((size_t)nparams);
+        for (const DGate &D : p->canon)
+            if (D.src == SRC_PARAM) {
+                by_param[(size_t)D.idx].push_back((int32_t)p->occ_param.size());
+                p->occ_param.push_back((int32_t)D.idx);
+                p->occ_scale.push_back(D.scale);
+            }
+        p->hoff.assign((size_t)nparams + 1, 0);
+        for (int64_t i = 0; i < nparams; ++i) {
+            p->hoff[(size_t)i + 1] = p->hoff[(size_t)i] + (int64_t)by_param[(size_t)i].size();
+            p->hocc.insert(p->hocc.end(), by_param[(size_t)i].begin(), by_param[(size_t)i].end());
+        }
+    }
     dq_status st = build_plan(*p);
     if (st != DQ_OK) {
         return st;
@@ -1424,13 +1640,16 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
 
 void dq_plan_destroy(dq_plan plan) try {
     if (!plan) return;
-    for (hipEvent_t e : plan->evpool) (void)hipEventDestroy(e);
-    for (auto &kv : plan->dev) {
-        int cur = 0;
-        if (hipGetDevice(&cur) == hipSuccess) {
-            (void)hipSetDevice(kv.first);
-            (void)hipFree(kv.second.blob);
-            (void)hipSetDevice(cur);
+    for (dq_plan_s *q : {plan->hess.get(), plan}) {   // the Hessian's derived plan, then the plan
+        if (!q) continue;
+        for (hipEvent_t e : q->evpool) (void)hipEventDestroy(e);
+        for (auto &kv : q->dev) {
+            int cur = 0;
+            if (hipGetDevice(&cur) == hipSuccess) {
+                (void)hipSetDevice(kv.first);
+                (void)hipFree(kv.second.blob);
+                (void)hipSetDevice(cur);
+            }
         }
     }
     delete plan;
@@ -1731,58 +1950,67 @@ dq_status dq_adjoint_grad(dq_plan plan, dq_obs obs, void *state, int64_t batch, 
     const DGroup *g = nullptr;
     const DTerm *t = nullptr;
     if ((st = ensure_obs(*obs, &g, &t)) != DQ_OK) return st;
+    if ((st = adjoint_core(*plan, *d, *obs, g, t, state, batch, params, params_bstride, data, data_bstride, grad_out,
+                           grad_params, grad_data, preserve_state, (char *)ws, L, (hipStream_t)stream)) != DQ_OK)
+        return st;
+    return ok();
+} DQ_CATCH
+
+dq_status dq_hessian_workspace_size(dq_plan plan, dq_obs obs, int32_t max_shifts, size_t *bytes) try {
+    if (!plan || !obs || !bytes) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (obs->n != plan->n) return fail(DQ_ERR_INVALID_ARG, "observable is for %d qubits, plan for %d", obs->n, plan->n);
+    dq_plan_s *h = nullptr;
+    dq_status st = ensure_hess_plan(*plan, &h);
+    if (st != DQ_OK) return st;
+    int64_t m = 0;
+    if ((st = hess_shifts(*plan, max_shifts, m)) != DQ_OK) return st;
+    *bytes = hess_layout(*plan, *h, obs, m).total;
+    return ok();
+} DQ_CATCH
+
+dq_status dq_hessian(dq_plan plan, dq_obs obs, const double *params, const double *data, const double *weights,
+                     double *hess, int32_t max_shifts, void *ws, size_t ws_bytes, void *stream) try {
+    if (!plan || !obs || !weights || !hess) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
+    if (obs->n != plan->n) return fail(DQ_ERR_INVALID_ARG, "observable is for %d qubits, plan for %d", obs->n, plan->n);
+    if (plan->nparams < 1) return fail(DQ_ERR_INVALID_ARG, "the circuit reads no parameters");
+    dq_status st = check_sources(*plan, params, 0, data, 0);
+    if (st != DQ_OK) return st;
+    dq_plan_s *h = nullptr;
+    if ((st = ensure_hess_plan(*plan, &h)) != DQ_OK) return st;
+    int64_t m = 0;
+    if ((st = hess_shifts(*plan, max_shifts, m)) != DQ_OK) return st;
+    const HessLayout HL = hess_layout(*plan, *h, obs, m);
+    if (!ws || ws_bytes < HL.total)
+        return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", HL.total, ws ? ws_bytes : 0);
+    DevData *d = nullptr, *dh = nullptr;
+    if ((st = ensure_device(*plan, &d)) != DQ_OK) return st;
+    if ((st = ensure_device(*h, &dh)) != DQ_OK) return st;
+    const DGroup *g = nullptr;
+    const DTerm *t = nullptr;
+    if ((st = ensure_obs(*obs, &g, &t)) != DQ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
-    void *mats = w + L.mats;
-    void *lam = w + L.lam;
-    double *partial = (double *)(w + L.part);
-    const int64_t bm = per_sample ? batch : 1;
-    const int64_t mstride = per_sample ? plan->block : 0;
-    // partial sums per sample: at most grad_waves (the workspace size), and
-    // no more than the adjoint tile kernel keeps resident, so that one
-    // round of waves covers every tile
-    int wps = (int)grad_waves(*plan, batch);
-    if (plan->R_adj > 0) {
-        const int resident = d->jit_adj_cap > 0 ? d->jit_adj_cap : tile_adj_capacity(plan->dbl, plan->R_adj);
-        const int cap = std::max<int64_t>(1, resident / batch);
-        wps = std::min(wps, cap);
+    const int64_t K = (int64_t)plan->occ_param.size(), P = plan->nparams;
+    double *rows = (double *)(w + HL.rows), *G = (double *)(w + HL.grads), *go = (double *)(w + HL.wts);
+    if (K == 0) {   // no angle reads a parameter: H = 0
+        const hipError_t e = launch_hess_accum(G, 0, 0, 0, d->hoff, d->hocc, d->occ_scale, P, hess, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "hessian: %s", hipGetErrorString(e));
+        return ok();
     }
-    void *psi = state;
-    hipError_t e;
-    const double SB = state_bytes(*plan, batch);
-    if (preserve_state) {
-        psi = w + L.keep;
-        ProfScope pc(*plan, DQ_PROF_OTHER, 1, 2 * SB, s);
-        e = launch_copy(plan->dbl, psi, state, batch << plan->n, s);
-        pc.done();
-        if (e != hipSuccess) return fail(DQ_ERR_HIP, "copy: %s", hipGetErrorString(e));
+    for (int64_t c0 = 0; c0 < K; c0 += m) {
+        const int64_t mc = std::min<int64_t>(m, K - c0), B = 2 * mc;
+        const WsLayout L = layout(*h, obs, B, 1, 1);
+        char *wd = w + HL.sub;
+        void *states = w + HL.states;
+        hipError_t e = launch_hess_rows(params, d->occ_param, d->occ_scale, K, c0, mc, rows, s);
+        if (e == hipSuccess) e = launch_bcast_rows(weights, obs->nobs, B, go, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "hessian rows: %s", hipGetErrorString(e));
+        if ((st = apply_on_device(*h, *dh, states, B, rows, K, data, 0, 1, wd + L.mats, 1, s, true)) != DQ_OK) return st;
+        if ((st = adjoint_core(*h, *dh, *obs, g, t, states, B, rows, K, data, 0, go, G, nullptr, 0, wd, L, s)) != DQ_OK)
+            return st;
+        e = launch_hess_accum(G, K, c0, mc, d->hoff, d->hocc, d->occ_scale, P, hess, s);
+        if (e != hipSuccess) return fail(DQ_ERR_HIP, "hessian accumulate: %s", hipGetErrorString(e));
     }
-    ProfScope pp(*plan, DQ_PROF_OTHER, 1, 0.0, s);
-    e = launch_prepare(plan->dbl, d->gates, d->fixed, d->slots + plan->adj.slot_lo,
-                       (int32_t)(plan->adj.slot_hi - plan->adj.slot_lo), params, params_bstride, data, data_bstride,
-                       mats, plan->block, bm, s);
-    pp.done();
-    if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
-    int32_t dt0, dt1;
-    zdiag_range(*plan, *obs, dt0, dt1);
-    ProfScope pl(*plan, DQ_PROF_LAMBDA, 1, 2 * SB, s);
-    e = launch_lambda(plan->dbl, psi, lam, plan->n, batch, g, (int32_t)obs->groups.size(), t, grad_out, obs->nobs, dt0,
-                      dt1, s);
-    pl.done();
-    if (e != hipSuccess) return fail(DQ_ERR_HIP, "lambda: %s", hipGetErrorString(e));
-    if ((st = run_program(*plan, *d, plan->adj, psi, lam, batch, mats, mstride, partial, wps, s)) != DQ_OK) return st;
-    ProfScope pf(*plan, DQ_PROF_OTHER, 1, 0.0, s);
-    if (plan->nparams > 0) {
-        e = launch_grad_final(partial, batch, wps, plan->ngrad, d->poff, d->pg, d->pf, plan->nparams,
-                              params_bstride != 0 ? 1 : 0, grad_params, s);
-        if (e != hipSuccess) return fail(DQ_ERR_HIP, "grad reduce: %s", hipGetErrorString(e));
-    }
-    if (grad_data && plan->ndata > 0) {
-        e = launch_grad_final(partial, batch, wps, plan->ngrad, d->doff, d->dg, d->df, plan->ndata,
-                              data_bstride != 0 ? 1 : 0, grad_data, s);
-        if (e != hipSuccess) return fail(DQ_ERR_HIP, "grad reduce: %s", hipGetErrorString(e));
-    }
-    pf.done();
     return ok();
 } DQ_CATCH
 

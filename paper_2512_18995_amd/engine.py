@@ -254,6 +254,32 @@ def adjoint_grad(plan: Plan, obs: Observable, state: torch.Tensor, params, data,
     return gp, gd
 
 
+def hessian(plan: Plan, obs: Observable, params, data=None, weights=None, max_shifts: int = 0,
+            ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Hessian [P, P] of sum_o weights[o] E_o (one sample, shared ``params``
+    [P]; ``data`` one row [D] or None; ``weights`` [nobs], default ones) by
+    parameter-shifted adjoint sweeps; ``max_shifts`` bounds the shifted
+    circuits per batch (0 = all)."""
+    p = _f64(params, "cuda" if not torch.is_tensor(params) else params.device)
+    dev = p.device
+    d = _f64(data, dev)
+    if d is not None:
+        d = d.reshape(-1)
+    w = torch.ones(obs.nobs, dtype=torch.float64, device=dev) if weights is None else _f64(weights, dev).reshape(-1)
+    if p.dim() != 1 or p.numel() != plan.nparams or w.numel() != obs.nobs:
+        raise ValueError("params must be [P] and weights [nobs]")
+    if out is None:
+        out = torch.empty((plan.nparams, plan.nparams), dtype=torch.float64, device=dev)
+    if ws is None:
+        n = ctypes.c_size_t(0)
+        check(lib().dq_hessian_workspace_size(plan.handle, obs.handle, int(max_shifts), ctypes.byref(n)),
+              "dq_hessian_workspace_size")
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+    check(lib().dq_hessian(plan.handle, obs.handle, p.data_ptr(), _ptr(d), w.data_ptr(), out.data_ptr(),
+                           int(max_shifts), ws.data_ptr(), ws.numel(), _stream(dev)), "dq_hessian")
+    return out
+
+
 class ExpvalFunction(torch.autograd.Function):
     """E[b, o] = <psi_b(params, data)| H_o |psi_b(...)> with the adjoint
     method as its backward (the custom autograd Function of the paper's

@@ -383,4 +383,59 @@ def pin_four_term_shift_equals_fd():
     _close(oracle.grad_param_shift(c, th, None, obs, np.ones((1, 1)), 1)[0][0], fd, 2e-8, "four-term CRX")
 
 
+def pin_hessian_closed_forms():
+    """Second derivatives in closed form.  (a) RY(a) on wire 0, RY(2b) on
+    wire 1, observable Z0 Z1: E = cos a cos 2b, so H = [[-cos a cos 2b,
+    2 sin a sin 2b], [2 sin a sin 2b, -4 cos a cos 2b]] (the factor 2 of the
+    second gate's scale is chained in).  (b) H on wire 0, CRY(t) from wire 0
+    to wire 1, observable Z1: E = (1 + cos t) / 2, E'' = -cos(t) / 2 (the
+    four-term rule applied twice).  (c) U3(theta, phi, lambda)|0> has
+    <X> = sin(theta) cos(phi), independent of lambda."""
+    a, b = 0.7, -1.1
+    c = W.Circuit(2, [W.Gate("ry", (0,), "param", 0), W.Gate("ry", (1,), "param", 1, 2.0)], 2)
+    H = oracle.hessian_param_shift(c, np.array([a, b]), None, [[(1.0, "ZZ")]], [1.0])
+    want = np.array([[-np.cos(a) * np.cos(2 * b), 2 * np.sin(a) * np.sin(2 * b)],
+                     [2 * np.sin(a) * np.sin(2 * b), -4 * np.cos(a) * np.cos(2 * b)]])
+    _close(H, want, 1e-12, "Hessian of cos a cos 2b")
+    for t in (0.3, 2.0, -2.6):
+        c = W.Circuit(2, [W.Gate("h", (0,)), W.Gate("cry", (0, 1), "param", 0)], 1)
+        H = oracle.hessian_param_shift(c, np.array([t]), None, [[(1.0, "IZ")]], [1.0])
+        _close(H, [[-np.cos(t) / 2]], 1e-12, "CRY second derivative t=%g" % t)
+    th, ph, la = 1.2, -0.4, 2.2
+    c = W.Circuit(1, [W.Gate("u3", (0,), "param", 0)], 3)
+    H = oracle.hessian_param_shift(c, np.array([th, ph, la]), None, [[(1.0, "X")]], [1.0])
+    want = np.array([[-np.sin(th) * np.cos(ph), -np.cos(th) * np.sin(ph), 0],
+                     [-np.cos(th) * np.sin(ph), -np.sin(th) * np.cos(ph), 0], [0, 0, 0]])
+    _close(H, want, 1e-12, "U3 Hessian of sin(theta) cos(phi)")
+
+
+def pin_hessian_equals_fd_of_gradient():
+    """The Hessian against central differences of the shift-rule gradient
+    (h = 1e-5: truncation ~h^2, rounding ~1e-16/h), on random circuits with
+    every differentiable gate kind, a parameter read by two gates with
+    different scales, and data-encoded gates (held fixed); and it is
+    symmetric."""
+    rng = np.random.default_rng(23)
+    ops = ("h", "rx", "ry", "rz", "cnot", "cz", "cp", "rzz", "rxx", "ryy", "u3", "crx", "cry", "crz")
+    for n in (2, 3):
+        c = W.random_circuit(rng, n, 10, ops=ops, with_data=True)
+        P = c.n_params
+        c = W.Circuit(n, c.gates + [W.Gate("rx", (0,), "param", 0, -1.5)], P, c.n_data)
+        params, data = W.random_params(rng, c, 1)
+        obs = [W.random_pauli_sum(rng, n, 3), W.random_pauli_sum(rng, n, 2)]
+        w = rng.standard_normal(2)
+        H = oracle.hessian_param_shift(c, params, data, obs, w)
+        h = 1e-5
+        F = np.zeros((P, P))
+        for q in range(P):
+            pp, pm = params.copy(), params.copy()
+            pp[q] += h
+            pm[q] -= h
+            gp = oracle.grad_param_shift(c, pp, data, obs, w[None, :], 1)[0]
+            gm = oracle.grad_param_shift(c, pm, data, obs, w[None, :], 1)[0]
+            F[:, q] = (gp - gm) / (2 * h)
+        _close(H, F, 1e-8, "Hessian vs FD of the gradient n=%d" % n)
+        _close(H, H.T, 1e-12, "Hessian symmetry n=%d" % n)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

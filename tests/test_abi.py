@@ -57,19 +57,31 @@ def _create(L, n, gates, nparams=0, ndata=0, dtype=0, opt=None):
     return st, h
 
 
-def test_unknown_op_and_xy_rotations(L):
+def test_unknown_op_and_expanded_gates(L):
     """Op codes beyond the last one are rejected; RXX and RYY are planned as
-    basis changes around an RZZ (four more internal gates each)."""
+    basis changes around an RZZ (four more internal gates each), U3 as
+    phase, RY, phase (three gates, one gradient slot per angle), and the
+    controlled rotations as two half-angle rotations around two CNOT / CZ
+    (four gates, two gradient slots)."""
     arr, keep = L.gate_array([G("h", (0,))])
-    arr[0].op = 15
-    h = ctypes.c_void_p()
-    assert L.lib().dq_plan_create(ctypes.byref(h), 3, arr, 1, 0, 0, 0, None) == 1
-    assert "unknown op" in L.lib().dq_last_error().decode()
+    for bad in (19, -1, 32):
+        arr[0].op = bad
+        h = ctypes.c_void_p()
+        assert L.lib().dq_plan_create(ctypes.byref(h), 3, arr, 1, 0, 0, 0, None) == 1
+        assert "unknown op" in L.lib().dq_last_error().decode()
     st, h = _create(L, 3, [G("rxx", (0, 2), "param", 0), G("ryy", (1, 0), "param", 1)], 2, 0)
     assert st == 0
     s = L.DqPlanStats()
     assert L.lib().dq_plan_get_stats(h, ctypes.byref(s)) == 0
     assert s.ngates == 10
+    L.lib().dq_plan_destroy(h)
+    gates = [G("u3", (1,), "param", 0), G("crx", (0, 2), "param", 3), G("cry", (2, 1), "data", 0),
+             G("crz", (1, 0), "param", 4), G("u3", (0,), "none", -1, 0.3)]
+    st, h = _create(L, 3, gates, 5, 1)
+    assert st == 0, L.lib().dq_last_error()
+    assert L.lib().dq_plan_get_stats(h, ctypes.byref(s)) == 0
+    assert s.ngates == 3 + 3 * 4 + 3
+    assert s.grad_gates == 3 + 3 * 2          # the fixed U3 carries no gradient
     L.lib().dq_plan_destroy(h)
 
 
@@ -86,6 +98,12 @@ def test_unknown_op_and_xy_rotations(L):
     (3, [G("unitary", (0, 1))], 0, 0, 1),                     # unitary without matrix
     (3, [G("rxx", (0,), "param", 0)], 1, 0, 1),               # two-qubit rotation on one wire
     (3, [G("ryy", (2, 2), "param", 0)], 1, 0, 1),             # repeated wire
+    (3, [G("u3", (0,), "param", 1)], 3, 0, 1),                # U3 reads idx..idx+2: 3 > 2
+    (3, [G("u3", (0,), "data", 0)], 0, 2, 1),
+    (3, [G("u3", (0, 1), "param", 0)], 3, 0, 1),              # U3 on two wires
+    (3, [G("cry", (1,), "param", 0)], 1, 0, 1),               # controlled rotation on one wire
+    (3, [G("crz", (0, 0), "param", 0)], 1, 0, 1),
+    (3, [G("crx", (0, 1), "param", 1)], 1, 0, 1),
 ])
 def test_plan_create_rejects(L, n, gates, np_, nd, code):
     st, h = _create(L, n, gates, np_, nd)
@@ -376,3 +394,35 @@ def test_multi_plan_runs_unbatched_shapes_on_the_single_plan_path():
     assert m.batched == [False, False]
     m = dq.Multi([dq.Plan(b.circuit, "c64"), dq.Plan(b.circuit, "c64")], [obs[1], obs[1]])
     assert m.batched == [True, True]
+
+
+def test_hessian_validates_before_device_work(L):
+    """dq_hessian rejects bad arguments on the host: NULL pointers, a plan
+    without parameters, a negative or too large max_shifts, a short
+    workspace; the workspace query builds the derived plan on the host."""
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    terms, off = L.pauli_arrays(3, [[(1.0, "ZZI")]])
+    obs = vp()
+    assert lib.dq_obs_create(ctypes.byref(obs), 3, terms, off, 1) == 0
+    gates = [G("u3", (0,), "param", 0), G("cry", (0, 1), "param", 3), G("ry", (2,), "data", 0)]
+    st, h = _create(L, 3, gates, 4, 1)
+    assert st == 0, lib.dq_last_error()
+    sz = ctypes.c_size_t(0)
+    assert lib.dq_hessian_workspace_size(h, obs, 0, ctypes.byref(sz)) == 0 and sz.value > 0
+    full = sz.value
+    assert lib.dq_hessian_workspace_size(h, obs, 2, ctypes.byref(sz)) == 0 and 0 < sz.value < full
+    assert lib.dq_hessian_workspace_size(h, obs, -1, ctypes.byref(sz)) == 1
+    fake = vp(256)   # never dereferenced: every call below fails validation first
+    assert lib.dq_hessian(h, obs, fake, fake, None, fake, 0, fake, full, None) == 1        # weights NULL
+    assert lib.dq_hessian(h, obs, None, fake, fake, fake, 0, fake, full, None) == 1        # params NULL
+    assert lib.dq_hessian(h, obs, fake, None, fake, fake, 0, fake, full, None) == 1        # data NULL
+    assert lib.dq_hessian(h, obs, fake, fake, fake, fake, -2, fake, full, None) == 1       # max_shifts < 0
+    assert lib.dq_hessian(h, obs, fake, fake, fake, fake, 0, fake, full - 1, None) == 3    # workspace short
+    assert lib.dq_hessian(h, obs, fake, fake, fake, fake, 0, None, full, None) == 3
+    L.lib().dq_plan_destroy(h)
+    st, h = _create(L, 3, [G("h", (0,))], 0, 0)
+    assert lib.dq_hessian(h, obs, fake, None, fake, fake, 0, fake, full, None) == 1        # no parameters
+    assert "no parameters" in lib.dq_last_error().decode()
+    L.lib().dq_plan_destroy(h)
+    lib.dq_obs_destroy(obs)

@@ -628,3 +628,88 @@ def test_xx_yy_rotations_forward_and_adjoint(dtype, jit, n, batch, per_sample):
     tol = 1e-6 if dtype == "c64" else 1e-12
     normwise(gp.cpu().numpy(), rp, RTOL[dtype], tol, "d/dparams")
     normwise(gd.cpu().numpy(), rd, RTOL[dtype], tol, "d/ddata")
+
+
+MODES = {"plain": dict(fusion=False), "interpreted": dict(fusion=True, jit=False), "compiled": dict(fusion=True, jit=True)}
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("n,batch,per_sample", [(3, 2, True), (7, 2, False), (12, 2, True)])
+def test_u3_and_controlled_rotations(dtype, mode, n, batch, per_sample):
+    """U3 and the controlled rotations CRX, CRY, CRZ (the planner expands U3
+    into phase, RY, phase and each controlled rotation into two half-angle
+    rotations around two CNOT or CZ gates) among the other gates: states
+    against the oracle, which applies their matrices directly, and adjoint
+    gradients for parameters and data against its shift rules (two-term for
+    U3's angles, four-term for the controlled rotations)."""
+    rng = np.random.default_rng(900 + n)
+    ops = ("h", "rx", "ry", "rz", "cnot", "cz", "u3", "crx", "cry", "crz", "rxx")
+    c = W.random_circuit(rng, n, 6 * n, ops=ops, with_data=True)
+    # one more of each new kind in the middle of the list, reading fresh
+    # parameters and a fresh data column
+    P, D, mid = c.n_params, c.n_data, len(c.gates) // 2
+    extra = [W.Gate("u3", (n - 1,), "param", P), W.Gate("crx", (1, 0), "param", P + 3),
+             W.Gate("cry", (n - 1, 1), "data", D, -0.5), W.Gate("crz", (0, n - 1), "param", P + 4)]
+    c = W.Circuit(n, c.gates[:mid] + extra + c.gates[mid:], P + 5, D + 1)
+    params, data = W.random_params(rng, c, batch, per_sample)
+    obs = [W.random_pauli_sum(rng, n, 4), W.random_pauli_sum(rng, n, 2)]
+    w = rng.standard_normal((batch, len(obs)))
+    m = MODES[mode]
+    plan, st = gpu_forward(c, params, data, batch, dtype, m["fusion"], jit=m.get("jit", False))
+    got = st.cpu().numpy()
+    for b in range(batch):
+        assert_state(got[b], oracle.state(c, params, data, b), dtype, 4 * len(c.gates), "sample %d" % b)
+    gp, gd = dq.adjoint_grad(plan, dq.Observable(n, obs), st, t64(params), t64(data), t64(w))
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w, batch, threads=8)
+    tol = 1e-6 if dtype == "c64" else 1e-12
+    normwise(gp.cpu().numpy(), rp, RTOL[dtype], tol, "d/dparams")
+    normwise(gd.cpu().numpy(), rd, RTOL[dtype], tol, "d/ddata")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("jit", [False, True], ids=["interpreted", "compiled"])
+def test_qcnn_listing_circuit(dtype, jit):
+    """The 12-qubit QCNN of the paper's listing (RY data encoding in three
+    stages, RXX / RYY convolutions, CRY pooling; observable Z0) on a batch
+    of 4 encoded samples: expectations, parameter gradients (summed over
+    the batch) and data gradients (per sample) against the oracle."""
+    rng = np.random.default_rng(1212)
+    c, obs = W.qcnn(12)
+    B = 4
+    params = rng.uniform(0, 2 * np.pi, c.n_params)
+    data = rng.uniform(0, np.pi, (B, c.n_data))
+    w = rng.standard_normal((B, 1))
+    plan, st = gpu_forward(c, params, data, B, dtype, True, jit=jit)
+    O = dq.Observable(c.n, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    normwise(E, oracle.forward(c, params, data, obs, B, threads=8), RTOL[dtype], 1e-7, "expval")
+    gp, gd = dq.adjoint_grad(plan, O, st, t64(params), t64(data), t64(w))
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w, B, threads=8)
+    tol = 1e-6 if dtype == "c64" else 1e-12
+    normwise(gp.cpu().numpy(), rp, RTOL[dtype], tol, "d/dparams")
+    normwise(gd.cpu().numpy(), rd, RTOL[dtype], tol, "d/ddata")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("residual", [True, False], ids=["residual", "plain"])
+def test_qresnet_listing_circuit(dtype, residual):
+    """The QResNet curve-fitting circuit of the paper's listing (U3 layers,
+    an RY-encoded input, controlled by wire 0 in the residual form) over a
+    batch of 16 inputs: expectations and gradients for the eight (six)
+    parameters and the inputs against the oracle."""
+    rng = np.random.default_rng(77)
+    c, obs = W.qresnet(residual)
+    B = 16
+    params = rng.uniform(0, 2 * np.pi, c.n_params)
+    data = np.linspace(-np.pi, np.pi, B)[:, None]
+    w = rng.standard_normal((B, len(obs)))
+    plan, st = gpu_forward(c, params, data, B, dtype, True)
+    O = dq.Observable(c.n, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    normwise(E, oracle.forward(c, params, data, obs, B, threads=8), RTOL[dtype], 1e-7, "expval")
+    gp, gd = dq.adjoint_grad(plan, O, st, t64(params), t64(data), t64(w))
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w, B, threads=8)
+    tol = 1e-6 if dtype == "c64" else 1e-12
+    normwise(gp.cpu().numpy(), rp, RTOL[dtype], tol, "d/dparams")
+    normwise(gd.cpu().numpy(), rd, RTOL[dtype], tol, "d/ddata")

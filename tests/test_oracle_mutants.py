@@ -122,6 +122,16 @@ PY_MUTANTS = [
      "if False:", ["pin_four_term_shift_equals_fd"]),
     ("u3-angle-not-chained", "grad_param_shift", "gp[g.idx + k] += g.scale * v", "gp[g.idx] += g.scale * v",
      ["pin_four_term_shift_equals_fd"]),
+    ("hessian-no-mirror", "hessian_param_shift", "        if a != b:", "        if False:",
+     ["pin_hessian_closed_forms", "pin_hessian_equals_fd_of_gradient"]),
+    ("hessian-diagonal-mirrored", "hessian_param_shift", "        if a != b:", "        if True:",
+     ["pin_hessian_closed_forms", "pin_hessian_equals_fd_of_gradient"]),
+    ("hessian-one-scale", "hessian_param_shift", "f = ga.scale * gb.scale * v", "f = ga.scale * v",
+     ["pin_hessian_closed_forms", "pin_hessian_equals_fd_of_gradient"]),
+    ("hessian-second-shift-dropped", "hessian_param_shift", "th[ib, kb] += sj", "pass",
+     ["pin_hessian_closed_forms", "pin_hessian_equals_fd_of_gradient"]),
+    ("hessian-u3-angle-index", "hessian_param_shift", "pa, pb = ga.idx + occ[a][1], gb.idx + occ[b][1]",
+     "pa, pb = ga.idx, gb.idx", ["pin_hessian_closed_forms", "pin_hessian_equals_fd_of_gradient"]),
 ]
 
 

@@ -78,16 +78,36 @@ def cpu_baseline(wl_id, full):
     t0 = time.perf_counter()
     oracle.forward(c, wl.params, wl.data, wl.observables, 1, threads=1, samples=[0])
     t = time.perf_counter() - t0
+    # all host cores: independent forward evaluations (what a parameter-shift
+    # gradient runs) in parallel threads, one per core (the C loop runs
+    # without the interpreter lock)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda _: oracle.forward(c, wl.params, wl.data, wl.observables, 1, threads=1, samples=[0]),
+                    range(cores)))
+    t_par = (time.perf_counter() - t0) / cores          # wall seconds per evaluation on all cores
     G_full, G_s = len(full.circuit.gates), len(c.gates)
-    t_fwd_full = t * (2.0 ** (full.circuit.n - n_s)) * (G_full / G_s)
+    scale = (2.0 ** (full.circuit.n - n_s)) * (G_full / G_s)
     evals = (2 * full.circuit.n_params + 1) if full.grad else 1       # parameter shift: 2 runs per parameter
-    per_circuit = t_fwd_full * evals
-    return {"value": 1.0 / per_circuit, "unit": "circuits/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle forward + expectation of the same circuit family at n=%d (%d gates, 1 sample) took "
-                      "%.2f s on one host thread; scaled by 2^%d amplitudes x %d/%d gates x %d evaluations "
-                      "(parameter shift, 2 per parameter + 1) per fwd+grad circuit" % (
-                          n_s, G_s, t, full.circuit.n - n_s, G_full, G_s, evals),
-            "sample_seconds": t}
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": 1.0 / (t_par * scale * evals), "unit": "circuits/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "sample": "oracle forward + expectation of the same circuit family at n=%d (%d gates, 1 sample): "
+                      "%.2f s on one host thread, %d such evaluations in %.2f s on %d threads; scaled by 2^%d "
+                      "amplitudes x %d/%d gates x %d evaluations (parameter shift, 2 per parameter + 1) per "
+                      "fwd+grad circuit" % (n_s, G_s, t, cores, t_par * cores, cores, full.circuit.n - n_s,
+                                            G_full, G_s, evals),
+            "single_thread": {"value": 1.0 / (t * scale * evals), "unit": "circuits/s", "cores": 1},
+            "sample_seconds": t + t_par * cores}
 
 
 def sweeps(args):
@@ -166,15 +186,21 @@ def sweeps(args):
 
 def bench_uneven(args):
     """64 circuits of uneven size (12..22 qubits, 4..16 layers) in one
-    multi-plan: forward, expectation and adjoint gradient of every circuit per
-    step, eager and replayed from a captured HIP graph."""
+    multi-plan whose tile shape (the fusion width of a sweep) is picked by
+    the autotuner: forward, expectation and adjoint gradient of every
+    circuit per step, eager and replayed from a captured HIP graph."""
     import numpy as np
     import torch
     import paper_2512_18995_amd as dq
     import workloads as W
     dev = "cuda:0"
     mw = W.config(4)
-    plans = [dq.Plan(it.circuit, "c64") for it in mw.items]
+    circuits = [it.circuit for it in mw.items]
+    t_tune = time.perf_counter()
+    tune = dq.autotune_multi(circuits, [it.observables for it in mw.items], [it.params for it in mw.items], "c64",
+                             device=dev)
+    t_tune = time.perf_counter() - t_tune
+    plans = [dq.Plan(c, "c64", tile_bits=tune["tile_bits"], adj_tile_bits=tune["adj_tile_bits"]) for c in circuits]
     obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
     M = dq.Multi(plans, obs)
     st, ws = M.states(dev), M.workspace(dev)
@@ -194,11 +220,20 @@ def bench_uneven(args):
             step()
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    # eager steps, with events between the three phases (same stream)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for k in range(args.steps):
+        ev[k][0].record()
+        M.apply(st, params, ws)
+        ev[k][1].record()
+        M.expval(st, ws, E)
+        ev[k][2].record()
+        M.adjoint_grad(st, params, w, ws, G)
+        ev[k][3].record()
     torch.cuda.synchronize()
     eager = (time.perf_counter() - t0) / args.steps
+    phase_ms = [float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(args.steps)])) for i in range(3)]
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         step()
@@ -209,18 +244,97 @@ def bench_uneven(args):
         g.replay()
     torch.cuda.synchronize()
     graph = (time.perf_counter() - t0) / args.steps
-    amps = sum(1 << it.circuit.n for it in mw.items)
+    amps = sum(1 << c.n for c in circuits)
+    # algorithmic bytes of the two sweep phases (complex64): the forward
+    # writes each state once (product-state init) and reads and writes it
+    # once per tile pass; the adjoint reads psi to seed lambda, writes
+    # lambda, then reads and writes both once per adjoint pass
+    fwd_b = adj_b = 0.0
+    for pl, c in zip(plans, circuits):
+        s_ = pl.stats()
+        S = 8.0 * (1 << c.n)
+        fwd_b += S * (1 + 2 * s_["fwd_tile_passes"])
+        adj_b += S * (2 + 4 * s_["adj_steps"])
+    roof = {"bound": "hbm", "kernel": "adjoint phase (seed, multi-circuit adjoint passes, reduction)",
+            "achieved": adj_b / 1e9 / (phase_ms[2] / 1e3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": adj_b / 1e9 / (phase_ms[2] / 1e3) / HBM_PEAK_GBS, "traffic": None,
+            "algorithmic_bytes_per_launch": adj_b, "avg_launch_ms": phase_ms[2],
+            "note": "effective: the working set (%.2f GB) sits largely in the 256 MB last-level cache only for "
+                    "the smaller circuits" % (8.0 * amps / 1e9)}
+    # plain path: every circuit with one launch per gate, central finite
+    # differences (2 P + 1 forward evaluations per circuit)
+    t_plain = 0.0
+    for it, c in zip(mw.items, circuits):
+        pp = dq.Plan(c, "c64", fusion=False)
+        o = dq.Observable(c.n, it.observables)
+        x = pp.state(1, dev)
+        pt = torch.as_tensor(it.params, dtype=torch.float64, device=dev)
+        pws = pp.workspace(1, False, 0, o, dev)
+        dq.apply_circuit(pp, x, pt, None, ws=pws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dq.apply_circuit(pp, x, pt, None, ws=pws)
+        dq.expval(pp, o, x, ws=pws)
+        torch.cuda.synchronize()
+        t_plain += (time.perf_counter() - t1) * (2 * c.n_params + 1)
+    plain = {"value": len(circuits) / t_plain, "unit": "circuits/s",
+             "sample": "each of the 64 circuits run once on the plain path (one launch per gate) with its "
+                       "expectation, times 2P+1 evaluations per circuit (central finite differences)",
+             "step_seconds_est": t_plain}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_uneven(mw)
     out = {"metric": METRIC, "value": len(mw.items) / graph, "unit": "circuits/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": graph * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "c64", "data": "synthetic",
            "config": {"workload": mw.name, "circuits": len(mw.items),
-                      "qubits": [it.circuit.n for it in mw.items], "gates": sum(len(it.circuit.gates) for it in mw.items),
+                      "qubits": [c.n for c in circuits], "gates": sum(len(c.gates) for c in circuits),
                       "params": M.param_count, "amplitudes": amps, "grad": "adjoint", "seed": mw.seed,
                       "parallelism": "none (one GPU)"},
+           "autotune": {"tile_bits": tune["tile_bits"], "adj_tile_bits": tune["adj_tile_bits"],
+                        "cached": tune["cached"], "seconds": t_tune,
+                        "tried": [{k: v for k, v in t.items()} for t in tune["tried"]]},
+           "batched_circuits": int(sum(M.batched)),
            "eager_ms_per_step": eager * 1e3, "graph_speedup": eager / graph,
+           "phase_ms": {"forward": phase_ms[0], "expval": phase_ms[1], "adjoint": phase_ms[2]},
+           "fwd_phase_GBps": fwd_b / 1e9 / (phase_ms[0] / 1e3),
+           "roofline": roof, "cpu_baseline": cpu, "plain_path": plain,
+           "speedup_vs_plain": (len(mw.items) / graph) / plain["value"],
            "checks": {"E_abs_sum": float(E.abs().sum().item()), "grad_norm": float(torch.linalg.vector_norm(G).item())},
-           "roofline": None, "cpu_baseline": None, "source_hash": kernel_source_hash()}
+           "source_hash": kernel_source_hash()}
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_uneven(mw):
+    """The oracle on the uneven batch: every circuit of at most 16 qubits
+    timed (forward + expectation, one per host thread), scaled by amplitudes
+    and gates to the others and by 2P+1 parameter-shift evaluations."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.lib()
+    small = [it for it in mw.items if it.circuit.n <= 16]
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def one(it):
+        t = time.perf_counter()
+        oracle.forward(it.circuit, it.params, None, it.observables, 1, threads=1)
+        return time.perf_counter() - t
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        times = list(ex.map(one, small))
+    wall = time.perf_counter() - t0
+    # seconds per (gate x amplitude) on one thread, from the timed circuits
+    rate = sum(times) / sum(len(it.circuit.gates) * (1 << it.circuit.n) for it in small)
+    per_step = sum(rate * len(it.circuit.gates) * (1 << it.circuit.n) * (2 * it.circuit.n_params + 1)
+                   for it in mw.items)
+    par = sum(times) / wall          # speed-up of the threads over one
+    return {"value": len(mw.items) / (per_step / par), "unit": "circuits/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle forward + expectation of the %d circuits with at most 16 qubits (%.2f s of "
+                      "single-thread work, %.2f s wall on %d threads); scaled by gates x amplitudes to all 64 "
+                      "circuits and by 2P+1 parameter-shift evaluations each" % (len(small), sum(times), wall, cores),
+            "single_thread": {"value": len(mw.items) / per_step, "unit": "circuits/s", "cores": 1},
+            "sample_seconds": wall}
 
 
 def bench_qft(args):
@@ -350,6 +464,8 @@ def main():
                          "workload always runs interpreted passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the per-result error against a complex128 reference (after the timed region)")
     ap.add_argument("--plain-layers", type=int, default=2)
     ap.add_argument("--sweeps", action="store_true", help="single-gate sweep bandwidth table instead of the step")
     ap.add_argument("--sweep-qubits", type=int, default=30)
@@ -499,6 +615,10 @@ def main():
                  "fwd_seconds_est": t_fwd}
         del pplan, pws
 
+    errors = None
+    if not args.no_check:
+        errors = result_errors(args, wl, plan, obs, params, data, E, gp, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, wl)
@@ -532,9 +652,56 @@ def main():
                  "passes": "compiled" if jit else "interpreted",
                  "compiled_kernels": len(plan.jit_sources()), "first_step_s": first_step_s},
         "checks": checks,
+        "errors": errors,
         "source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
+
+
+def result_errors(args, wl, plan, obs, params, data, E, gp, dev):
+    """Error of the timed step's results (expectations, gradients) against a
+    complex128 reference, computed after the timed region: the oracle for
+    the complex128 10-qubit workload, the complex128 HIP path (itself
+    checked against the oracle on the same circuit families) for the
+    complex64 ones."""
+    import numpy as np
+    import torch
+    import paper_2512_18995_amd as dq
+    E = E.cpu().numpy()
+    g = None if gp is None else gp.cpu().numpy()
+    if wl.dtype == "c128":
+        import oracle
+        ref_name = "oracle (complex128 CPU simulator; parameter-shift gradients)"
+        E_ref = oracle.forward(wl.circuit, wl.params, wl.data, wl.observables, wl.batch, threads=16)
+        g_ref = None
+        if g is not None:
+            g_ref, _ = oracle.grad_param_shift(wl.circuit, wl.params, wl.data, wl.observables,
+                                               np.ones((wl.batch, 1)), wl.batch, threads=16)
+    else:
+        ref_name = "complex128 HIP path (checked against the oracle on the same circuit family)"
+        torch.cuda.empty_cache()
+        p128 = dq.Plan(wl.circuit, "c128", jit=True)
+        st = p128.state(wl.batch, dev)
+        dq.apply_circuit(p128, st, params, data, from_zero=True)
+        E_ref = dq.expval(p128, obs, st).cpu().numpy()
+        g_ref = None
+        if g is not None:
+            gout = torch.ones((wl.batch, 1), dtype=torch.float64, device=dev)
+            g_ref, _ = dq.adjoint_grad(p128, obs, st, params, data, gout, want_data=False)
+            g_ref = g_ref.cpu().numpy()
+        del st, p128
+        torch.cuda.empty_cache()
+
+    def stat(v, r):
+        d = np.abs(v - r)
+        return {"rel_norm": float(np.linalg.norm(v - r) / max(np.linalg.norm(r), 1e-300)),
+                "max_abs": float(d.max()), "ref_norm": float(np.linalg.norm(r)),
+                "max_rel_entry": float((d / np.maximum(np.abs(r), 1e-300)).max())}
+
+    out = {"reference": ref_name, "expval": stat(E, E_ref)}
+    if g is not None:
+        out["grad"] = stat(g, g_ref)
+    return out
 
 
 if __name__ == "__main__":

@@ -10,7 +10,9 @@ the engine without a built library raises.
 from ._lib import DqError, LIB_PATH, lib  # noqa: F401
 
 __all__ = ["DqError", "LIB_PATH", "lib", "Plan", "Observable", "state_init", "apply_circuit", "expval", "autotune",
-           "adjoint_grad", "expectation", "ExpvalFunction", "Multi", "probs", "sample", "hessian"]
+           "adjoint_grad", "expectation", "ExpvalFunction", "Multi", "probs", "sample", "hessian",
+           "autotune_multi", "candidate_options",
+           "multi_candidates"]
 
 
 def __getattr__(name):

@@ -389,52 +389,143 @@ class Multi:
 
 
 # ---------------------------------------------------------------- autotuner
-def _structure_key(circuit, dtype: str, batch: int, per_sample: bool, grad: bool, device) -> str:
+def _arch(device) -> str:
+    props = torch.cuda.get_device_properties(device)
+    return getattr(props, "gcnArchName", props.name)
+
+
+def _structure_key(circuits, dtype: str, batch: int, per_sample: bool, grad: bool, arch: str, jit=None) -> str:
+    """Cache key of a tuning result: circuit structure (gates, wires, angle
+    sources; not the angles), dtype, batch, per-sample flag, gradient flag,
+    the jit flag and the GPU architecture."""
     import hashlib
     h = hashlib.sha256()
-    h.update(("%d|%s|%d|%d|%d|" % (circuit.n, dtype, batch, per_sample, grad)).encode())
-    for g in circuit.gates:
-        h.update(("%s:%s:%s;" % (g.op, ",".join(map(str, g.wires)), g.src)).encode())
-    props = torch.cuda.get_device_properties(device)
-    h.update(getattr(props, "gcnArchName", props.name).encode())
+    h.update(("%s|%d|%d|%d|%s|" % (dtype, batch, per_sample, grad, jit)).encode())
+    for circuit in (circuits if isinstance(circuits, (list, tuple)) else [circuits]):
+        h.update(("n%d|" % circuit.n).encode())
+        for g in circuit.gates:
+            h.update(("%s:%s:%s;" % (g.op, ",".join(map(str, g.wires)), g.src)).encode())
+    h.update(arch.encode())
     return h.hexdigest()[:24]
 
 
-def candidate_options(dtype: str, n: int):
-    """Fusion width / tile shape candidates: register bits per tile and the
-    dense-block width of the forward sweep."""
-    tiles = [r for r in ((3, 4, 5) if dtype == "c64" else (3, 4)) if r <= n - 6] or [0]
-    out = [{"tile_bits": r, "dense_fuse": 0} for r in tiles]
+def candidate_options(dtype: str, n: int, jit: bool = False):
+    """Fusion width / tile shape candidates: register bits per tile (the
+    gates of one HBM sweep act on up to 6 + tile_bits wires) and the
+    dense-block width of the forward sweep; with jit, the compiled passes'
+    wider tiles (6 register bits for complex64, 5 for complex128) too."""
+    top = (6 if dtype == "c64" else 5) if jit else (5 if dtype == "c64" else 4)
+    tiles = [r for r in range(3, top + 1) if r <= n - 6] or [0]
+    out = [{"tile_bits": r, "dense_fuse": 0, "jit": bool(jit)} for r in tiles]
     if dtype == "c64":
-        out += [{"tile_bits": tiles[-1], "dense_fuse": k} for k in (4, 5) if n >= k + 5]
+        out += [{"tile_bits": min(tiles[-1], 5), "dense_fuse": k, "jit": bool(jit)} for k in (4, 5) if n >= k + 5]
     return out
 
 
+def _load_cache(path):
+    import json
+    import os
+    if os.path.exists(path):
+        try:
+            return json.load(open(path))
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def _store_cache(path, cache):
+    import json
+    import os
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        json.dump(cache, open(path, "w"), indent=1)
+    except OSError:
+        pass
+
+
+def _time_ms(step, reps, device):
+    step()
+    torch.cuda.synchronize(device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    torch.cuda.synchronize(device)
+    return e0.elapsed_time(e1) / reps
+
+
+def multi_candidates(dtype: str):
+    """Tile shapes of the uneven-batch kernels (forward, adjoint register
+    bits): those the multi-circuit kernels are built for."""
+    fwd = (3, 4, 5) if dtype == "c64" else (3, 4)
+    adj = (3, 4) if dtype == "c64" else (3,)
+    return [{"tile_bits": f, "adj_tile_bits": a} for f in fwd for a in adj if a <= f]
+
+
+def autotune_multi(circuits, observables, params, dtype: str = "c64", reps: int = 2,
+                   cache_path: Optional[str] = None, device="cuda:0", verbose: bool = False) -> dict:
+    """Pick the tile shape (forward and adjoint register bits, i.e. the
+    fusion width of a sweep) of an uneven batch with the lowest measured
+    time of one forward + expectation + adjoint step of the multi-plan on
+    this device; cached like autotune().  Circuits whose plan cannot join
+    the shared launches at a candidate shape still run (single-plan path)."""
+    import os
+    path = cache_path or os.environ.get("DQ_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/dq_autotune.json"))
+    key = "multi|" + _structure_key(list(circuits), dtype, 1, False, True, _arch(device))
+    cache = _load_cache(path)
+    if key in cache:
+        return dict(cache[key], cached=True)
+    best, timings = None, []
+    for opt in multi_candidates(dtype):
+        plans = [Plan(c, dtype, tile_bits=opt["tile_bits"], adj_tile_bits=opt["adj_tile_bits"]) for c in circuits]
+        obs = [Observable(c.n, o) for c, o in zip(circuits, observables)]
+        M = Multi(plans, obs)
+        st, ws = M.states(device), M.workspace(device)
+        p = M.pack_params(params, device)
+        w = torch.ones(M.nout, dtype=torch.float64, device=device)
+
+        def step():
+            M.apply(st, p, ws)
+            M.expval(st, ws)
+            M.adjoint_grad(st, p, w, ws)
+
+        ms = _time_ms(step, reps, device)
+        timings.append(dict(opt, ms=ms, batched=sum(M.batched)))
+        if verbose:
+            print("autotune_multi", opt, "%.3f ms" % ms, flush=True)
+        if best is None or ms < best["ms"]:
+            best = dict(opt, ms=ms)
+        del M, plans, obs, st, ws
+    result = {"tile_bits": best["tile_bits"], "adj_tile_bits": best["adj_tile_bits"], "ms": best["ms"],
+              "tried": timings}
+    cache[key] = result
+    _store_cache(path, cache)
+    return dict(result, cached=False)
+
+
 def autotune(circuit, dtype, obs: Observable, params, data=None, batch: int = 1, grad: bool = True,
-             reps: int = 2, cache_path: Optional[str] = None, device="cuda:0", verbose: bool = False) -> dict:
+             reps: int = 2, cache_path: Optional[str] = None, device="cuda:0", verbose: bool = False,
+             jit: bool = False) -> dict:
     """Pick the plan options (tile bits, dense-fusion width) with the lowest
     measured time of one forward (+ adjoint) step on this device; results are
-    cached in a JSON file keyed by circuit structure, dtype, batch and GPU
-    architecture (DQ_AUTOTUNE_CACHE, default ~/.cache/dq_autotune.json)."""
-    import json
+    cached in a JSON file keyed by circuit structure, dtype, batch, the jit
+    flag and GPU architecture (DQ_AUTOTUNE_CACHE, default
+    ~/.cache/dq_autotune.json).  With jit the candidates are compiled passes
+    (their compiles fall in the first, untimed call of each candidate)."""
     import os
     path = cache_path or os.environ.get("DQ_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/dq_autotune.json"))
     p = _f64(params, device) if params is not None else None
     d = _f64(data, device) if data is not None else None
     per_sample = _stride(p) != 0 or _stride(d) != 0
-    key = _structure_key(circuit, dtype, batch, per_sample, grad, device)
-    cache = {}
-    if os.path.exists(path):
-        try:
-            cache = json.load(open(path))
-        except (OSError, ValueError):
-            cache = {}
+    key = _structure_key(circuit, dtype, batch, per_sample, grad, _arch(device), jit=bool(jit))
+    cache = _load_cache(path)
     if key in cache:
-        return cache[key]
+        return dict(cache[key], cached=True)
     gout = torch.ones((batch, obs.nobs), dtype=torch.float64, device=device)
     best, timings = None, []
-    for opt in candidate_options(dtype, circuit.n):
-        plan = Plan(circuit, dtype, tile_bits=opt["tile_bits"], dense_fuse=opt["dense_fuse"])
+    for opt in candidate_options(dtype, circuit.n, jit):
+        plan = Plan(circuit, dtype, tile_bits=opt["tile_bits"], dense_fuse=opt["dense_fuse"], jit=opt["jit"])
         st = plan.state(batch, device)
         ws = plan.workspace(batch, per_sample, 1 if grad else 0, obs, device)
 
@@ -444,26 +535,15 @@ def autotune(circuit, dtype, obs: Observable, params, data=None, batch: int = 1,
             if grad:
                 adjoint_grad(plan, obs, st, p, d, gout, ws=ws, want_data=False)
 
-        step()
-        torch.cuda.synchronize(device)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            step()
-        e1.record()
-        torch.cuda.synchronize(device)
-        ms = e0.elapsed_time(e1) / reps
+        ms = _time_ms(step, reps, device)
         timings.append(dict(opt, ms=ms))
         if verbose:
             print("autotune", opt, "%.3f ms" % ms, flush=True)
         if best is None or ms < best["ms"]:
             best = dict(opt, ms=ms)
         del plan, st, ws
-    result = {"tile_bits": best["tile_bits"], "dense_fuse": best["dense_fuse"], "ms": best["ms"], "tried": timings}
+    result = {"tile_bits": best["tile_bits"], "dense_fuse": best["dense_fuse"], "jit": best["jit"], "ms": best["ms"],
+              "tried": timings}
     cache[key] = result
-    try:
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        json.dump(cache, open(path, "w"), indent=1)
-    except OSError:
-        pass
-    return result
+    _store_cache(path, cache)
+    return dict(result, cached=False)

@@ -123,14 +123,15 @@ def test_config5_32_qubits_properties():
     E2 = dq.expval(p128, obs, st).cpu().numpy()
     g2, _ = dq.adjoint_grad(p128, obs, st, p, None, t64(np.ones((1, 1))))
     g2 = g2.cpu().numpy()
-    # complex64 at 1920 gates: the expectation holds the 1e-5 target; the
-    # gradient entries are sums over 2^32 amplitudes that cancel to ~1e-4
-    # of |<lambda|psi>| scale (||g|| ~ 5e-3 against ||H psi|| ~ 5.6), which
-    # amplifies the state's complex64 rounding (~1e-7 relative per pass) to
-    # ~1e-4 normwise (measured 1.1e-4); the complex128 path, checked against
-    # central differences below, carries the 1e-5 claim at this size
+    # complex64 at 1920 gates: the expectation holds the 1e-5 target
+    # (measured 9e-8); the gradient does not: its absolute error is about
+    # 2e-7 at 20 layers for every register size from 24 to 32 qubits, while
+    # ||g|| shrinks with the register (2.5e-2 at 24 qubits, 5.4e-3 at 32),
+    # so the normwise error grows to 4.2e-5 here (1.0e-5 at 24 qubits).
+    # The bound is twice the measured error; the complex128 path, checked
+    # against central differences below, carries the 1e-5 claim at this size
     rel_e = normwise(E[0], E2[0], RTOL["c64"], 0.0, "expval complex64 vs complex128")
-    rel_g = normwise(g, g2, 1e-3, 0.0, "gradient complex64 vs complex128")
+    rel_g = normwise(g, g2, 8.5e-5, 0.0, "gradient complex64 vs complex128")
     print("config 5: complex64 vs complex128 relative error: expval %.2e, gradient %.2e" % (rel_e, rel_g), flush=True)
     print("config 5: complex128 adjoint done", flush=True)
     h = 1e-4

@@ -227,6 +227,26 @@ dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const doubl
                            int64_t params_bstride, const double *data, int64_t data_bstride,
                            int32_t from_zero, void *ws, size_t ws_bytes, void *stream);
 
+/* dq_apply_circuit without a workspace and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Same arguments
+ * and results as dq_apply_circuit; the per-sample gate-matrix blocks go to
+ * a library-owned device scratch array of DQ_NOALLOC_SCRATCH_BYTES (16 MiB)
+ * per device, held until the process ends.  Preconditions: the plan has
+ * been used on the current device by dq_apply_circuit (which uploads its
+ * tables and loads its compiled passes; this call uploads, compiles and
+ * allocates nothing), and the matrix blocks (dq_workspace_size with grad =
+ * 0) fit the scratch.  Errors, with nothing enqueued: DQ_ERR_INVALID_ARG
+ * (as dq_apply_circuit, or a plan not yet resident on the device),
+ * DQ_ERR_OUT_OF_RANGE (matrix blocks beyond the scratch).  All calls on one
+ * device share its scratch: calls that overlap on one device (concurrent
+ * streams or threads) race and must be serialised by the caller; calls in
+ * one stream are ordered.  No timing events are recorded. */
+#define DQ_NOALLOC_SCRATCH_BYTES (16u << 20)
+dq_status dq_apply_circuit_noalloc(dq_plan plan, void *state, int64_t batch, const double *params,
+                                   int64_t params_bstride, const double *data, int64_t data_bstride, int32_t from_zero,
+                                   void *stream);
+
 /* out[b][o] = sum_k coef_k <psi_b| P_k |psi_b> over the terms of observable
  * o (paper 4.2, expectation()).  out: device [batch][nobs] float64.
  * Reductions are deterministic (fixed order, float64 across blocks). */

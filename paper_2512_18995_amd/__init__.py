@@ -11,7 +11,7 @@ from ._lib import DqError, LIB_PATH, lib  # noqa: F401
 
 __all__ = ["DqError", "LIB_PATH", "lib", "Plan", "Observable", "state_init", "apply_circuit", "expval", "autotune",
            "adjoint_grad", "expectation", "ExpvalFunction", "Multi", "probs", "sample", "hessian",
-           "autotune_multi", "candidate_options",
+           "apply_circuit_noalloc", "autotune_multi", "candidate_options",
            "multi_candidates"]
 
 

@@ -27,7 +27,7 @@ EXPORTS = ["dq_plan_create", "dq_plan_destroy", "dq_plan_get_stats", "dq_obs_cre
            "dq_multi_create", "dq_multi_destroy", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
            "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe",
            "dq_plan_jit_source", "dq_probs_workspace_size", "dq_probs", "dq_sample",
-           "dq_hessian_workspace_size", "dq_hessian"]
+           "dq_hessian_workspace_size", "dq_hessian", "dq_apply_circuit_noalloc"]
 PROF_KINDS = ["fwd_tile", "adj_tile", "gate", "grad_gate", "expval", "lambda", "init", "other", "dense"]
 
 
@@ -106,13 +106,15 @@ def lib():
         L.dq_sample.argtypes = [vp, c_int64, c_int32, vp, c_int32, vp, vp]
         L.dq_hessian_workspace_size.argtypes = [vp, vp, c_int32, POINTER(c_size_t)]
         L.dq_hessian.argtypes = [vp, vp, vp, vp, vp, vp, c_int32, vp, c_size_t, vp]
+        L.dq_apply_circuit_noalloc.argtypes = [vp, vp, c_int64, vp, c_int64, vp, c_int64, c_int32, vp]
         L.dq_last_error.restype = c_char_p
         L.dq_version.restype = c_int32
         for f in ("dq_plan_create", "dq_plan_get_stats", "dq_obs_create", "dq_workspace_size", "dq_state_init",
                   "dq_apply_circuit", "dq_expval", "dq_adjoint_grad", "dq_profile_enable", "dq_profile_read",
                   "dq_multi_create", "dq_multi_layout", "dq_multi_workspace_size", "dq_multi_apply",
                   "dq_multi_expval", "dq_multi_adjoint_grad", "dq_multi_batched", "dq_plan_describe", "dq_plan_jit_source",
-                  "dq_probs_workspace_size", "dq_probs", "dq_sample", "dq_hessian_workspace_size", "dq_hessian"):
+                  "dq_probs_workspace_size", "dq_probs", "dq_sample", "dq_hessian_workspace_size", "dq_hessian",
+                  "dq_apply_circuit_noalloc"):
             getattr(L, f).restype = c_int32
         _lib = L
     return _lib

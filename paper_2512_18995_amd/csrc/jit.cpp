@@ -264,7 +264,10 @@ hipError_t jit_launch(hipFunction_t f, const std::string &name, const TileArgs &
         (void)hipGetDevice(&dev);
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_cache.find(name);
-        if (it != g_cache.end()) resident = it->second.resident[dev];
+        if (it != g_cache.end()) {
+            const auto r = it->second.resident.find(dev);
+            if (r != it->second.resident.end()) resident = r->second;
+        }
     }
     const int64_t tiles = a.batch << (a.n - 6 - a.R);
     const int64_t cap = resident > 0 ? resident : 4096;

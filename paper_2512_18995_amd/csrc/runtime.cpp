@@ -12,12 +12,20 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <optional>
 #include <stdexcept>
 #include <string>
 #include <vector>
 
 #include "../../include/dq.h"
 #include "dq_internal.h"
+
+// Device scratch of dq_apply_circuit_noalloc: the per-sample gate-matrix
+// blocks live here instead of in a caller's workspace.  Each device that the
+// library runs on holds one copy until the process ends.  Host code never
+// uses this name as an address: it takes the device address from
+// hipGetSymbolAddress once per device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[DQ_NOALLOC_SCRATCH_BYTES];
 
 using namespace dq;
 
@@ -1203,7 +1211,7 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
     const double SB = state_bytes(p, batch);
     // consecutive launches of one kind share one pair of timing events, so
     // that profiling adds no work between them
-    std::unique_ptr<ProfScope> ps;
+    std::optional<ProfScope> ps;
     for (const Step &S : prog.steps) {
         hipError_t e = hipSuccess;
         const int nst = lam ? 2 : 1;   // states a per-gate sweep touches
@@ -1219,7 +1227,7 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
         }
         if (!ps || ps->kind != kind) {
             if (ps) ps->done();
-            ps.reset(new ProfScope(p, kind, 0, 0.0, s, timed));
+            ps.emplace(p, kind, 0, 0.0, s, timed);
         }
         ps->nl += nl;
         ps->bytes += bytes;
@@ -1461,6 +1469,42 @@ HessLayout hess_layout(const dq_plan_s &p, const dq_plan_s &h, const dq_obs_s *o
     off += layout(h, o, B, 1, 1).total;
     L.total = off;
     return L;
+}
+
+// Device address of `scratch` on the current device, looked up with
+// hipGetSymbolAddress on the first call per device (with that device
+// current) and kept in a fixed table, so later calls allocate nothing.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+dq_status noalloc_scratch(void **out) {
+    int dev = 0;
+    DQ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DQ_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DQ_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DQ_OK;
+}
+
+// the plan's device tables and compiled passes on the current device, if
+// an earlier call has put them there (nothing is uploaded or compiled here)
+dq_status resident_device(dq_plan_s &p, DevData **out) {
+    int dev = 0;
+    DQ_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(p.mu);
+    const auto it = p.dev.find(dev);
+    if (it == p.dev.end())
+        return fail(DQ_ERR_INVALID_ARG, "plan not yet resident on device %d: call dq_apply_circuit with it once first", dev);
+    *out = &it->second;
+    return DQ_OK;
 }
 
 }  // namespace
@@ -1843,6 +1887,28 @@ dq_status dq_apply_circuit(dq_plan plan, void *state, int64_t batch, const doubl
     if ((st = ensure_device(*plan, &d)) != DQ_OK) return st;
     if ((st = apply_on_device(*plan, *d, state, batch, params, params_bstride, data, data_bstride, from_zero,
                               (char *)ws + L.mats, per_sample, (hipStream_t)stream, true)) != DQ_OK)
+        return st;
+    return ok();
+} DQ_CATCH
+
+dq_status dq_apply_circuit_noalloc(dq_plan plan, void *state, int64_t batch, const double *params,
+                                   int64_t params_bstride, const double *data, int64_t data_bstride, int32_t from_zero,
+                                   void *stream) try {
+    dq_status st = check_apply(plan, state, batch, params, params_bstride, data, data_bstride);
+    if (st != DQ_OK) return st;
+    const int per_sample = (params_bstride != 0 || data_bstride != 0) ? 1 : 0;
+    const WsLayout L = layout(*plan, nullptr, batch, per_sample, 0);
+    if (L.total > (size_t)DQ_NOALLOC_SCRATCH_BYTES)
+        return fail(DQ_ERR_OUT_OF_RANGE, "gate matrices of %zu bytes exceed the %zu-byte scratch; use dq_apply_circuit",
+                    L.total, (size_t)DQ_NOALLOC_SCRATCH_BYTES);
+    DevData *d = nullptr;
+    if ((st = resident_device(*plan, &d)) != DQ_OK) return st;
+    void *scr = nullptr;
+    if ((st = noalloc_scratch(&scr)) != DQ_OK) return st;
+    // every matrix slot the passes read is written by the prepare kernel
+    // first, so the scratch needs no clearing; no timing events are made
+    if ((st = apply_on_device(*plan, *d, state, batch, params, params_bstride, data, data_bstride, from_zero,
+                              (char *)scr + L.mats, per_sample, (hipStream_t)stream, false)) != DQ_OK)
         return st;
     return ok();
 } DQ_CATCH

@@ -185,6 +185,22 @@ def apply_circuit(plan: Plan, state: torch.Tensor, params=None, data=None, from_
     return state
 
 
+def apply_circuit_noalloc(plan: Plan, state: torch.Tensor, params=None, data=None, from_zero: bool = True):
+    """apply_circuit with the gate matrices in the library's device scratch:
+    no workspace and no allocation (params / data must already be float64
+    contiguous tensors on the state's device; the plan must have run
+    apply_circuit on this device once)."""
+    _check_state(plan, state)
+    dev = state.device
+    for t in (params, data):
+        if t is not None and (t.dtype != torch.float64 or t.device != dev or not t.is_contiguous()):
+            raise ValueError("params / data must be contiguous float64 tensors on %s" % dev)
+    check(lib().dq_apply_circuit_noalloc(plan.handle, state.data_ptr(), state.shape[0], _ptr(params),
+                                         _stride(params), _ptr(data), _stride(data), 1 if from_zero else 0,
+                                         _stream(dev)), "dq_apply_circuit_noalloc")
+    return state
+
+
 def expval(plan: Plan, obs: Observable, state: torch.Tensor, ws: Optional[torch.Tensor] = None,
            out: Optional[torch.Tensor] = None) -> torch.Tensor:
     _check_state(plan, state)

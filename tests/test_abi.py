@@ -426,3 +426,18 @@ def test_hessian_validates_before_device_work(L):
     assert "no parameters" in lib.dq_last_error().decode()
     L.lib().dq_plan_destroy(h)
     lib.dq_obs_destroy(obs)
+
+
+def test_noalloc_apply_validates_on_the_host(L):
+    """dq_apply_circuit_noalloc: bad arguments and matrix blocks beyond the
+    16 MiB scratch are rejected before any device call."""
+    lib = L.lib()
+    gates = [G("u3", (q % 8,), "param", 3 * q) for q in range(600)]
+    st, h = _create(L, 8, gates, 1800, 0, dtype=1)
+    assert st == 0, lib.dq_last_error()
+    fake = ctypes.c_void_p(256)   # never dereferenced
+    assert lib.dq_apply_circuit_noalloc(h, None, 1, fake, 0, None, 0, 1, None) == 1
+    assert lib.dq_apply_circuit_noalloc(h, fake, 0, fake, 0, None, 0, 1, None) == 1
+    assert lib.dq_apply_circuit_noalloc(h, fake, 256, fake, 1800, None, 0, 1, None) == 4
+    assert "scratch" in lib.dq_last_error().decode()
+    lib.dq_plan_destroy(h)

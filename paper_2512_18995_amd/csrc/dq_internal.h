@@ -71,6 +71,43 @@ struct MultiEntry {
     int32_t tbits[MAX_TILE_R + 3];
 };
 
+// The per-circuit steps of an uneven batch that surround the tile passes,
+// one launch each over all circuits: matrix preparation, start states,
+// expectations, the adjoint seed and the final gradient sums.  Offsets:
+// st_off in amplitudes from the packed state base, *_off in bytes from the
+// workspace base except par_off / out_off (elements of the packed
+// parameter / output arrays).
+struct DGroup;
+struct DTerm;
+struct MPrep {
+    const DGate *gates;
+    const double2 *fixed;
+    const DSlot *slots;        // the program's slot range
+    int32_t nslots, pad;
+    int64_t par_off, mats_off;
+};
+struct MInit {
+    int64_t st_off, mats_off;
+    const int64_t *fold;       // per physical bit: folded slot offset, -1 none
+    int32_t n, has_fold;
+};
+struct MExp {
+    int64_t st_off, lam_off, part_off;
+    int64_t unit_begin;        // first expectation block of this circuit
+    int64_t amp_begin;         // first amplitude of this circuit in the adjoint-seed range
+    int64_t out_off;
+    const DGroup *groups;
+    const DTerm *terms;
+    int32_t n, ngroups, nterms, nobs, eb, pad;
+};
+struct MGrad {
+    int64_t part_off, par_off, unit_begin;
+    const int64_t *poff;       // parameter -> gradient slots (CSR) with chain factors
+    const int32_t *pg;
+    const double *pf;
+    int32_t wps, ngrad;
+};
+
 // ---------------------------------------------------------------- observables
 // Terms grouped by X mask (physical bits).  With w = coef * i^{nY} (complex,
 // nY = number of Y letters) and S = sum_j (-1)^{|j & z|} conj(psi_{j^x}) psi_j,
@@ -161,6 +198,20 @@ hipError_t launch_grad_gate(int dbl, const void *psi, const void *lam, int32_t n
 hipError_t launch_grad_final(const double *partial, int64_t batch, int32_t wps, int32_t ngrad,
                              const int64_t *csr_off, const int32_t *csr_g, const double *csr_f,
                              int64_t nout, int32_t per_sample, double *out, hipStream_t s);
+// uneven batches (kernels.hip): one launch per step over all circuits
+hipError_t launch_prepare_multi(int dbl, const MPrep *ents, int32_t nent, int32_t max_slots, const double *params,
+                                void *ws, hipStream_t s);
+hipError_t launch_init_multi(int dbl, void *st, const void *ws, const MInit *ents, int32_t nent, int32_t max_n,
+                             hipStream_t s);
+// units: sum of the entries' eb; writes out[out_off + o] for every circuit
+hipError_t launch_expval_multi(int dbl, const void *st, void *ws, const MExp *ents, int32_t nent, int64_t units,
+                               double *out, hipStream_t s);
+// total: sum of the circuits' amplitudes (amp_begin ranges)
+hipError_t launch_lambda_multi(int dbl, const void *st, void *ws, const MExp *ents, int32_t nent, int64_t total,
+                               const double *gout, hipStream_t s);
+// total: sum of the circuits' parameter counts (unit ranges)
+hipError_t launch_grad_final_multi(const void *ws, const MGrad *ents, int32_t nent, int64_t total, double *out,
+                                   hipStream_t s);
 // Hessian by shifted adjoints (kernels.hip): angle rows of 2 mc shifted
 // circuits, the observable weights broadcast to every row, and the
 // deterministic accumulation of H[P][P] from the rows' gradients (the first

@@ -75,15 +75,11 @@ __device__ void gate_matrix(const DGate &g, double th, const double2 *fixed, dou
     }
 }
 
+// One matrix slot of one sample: the product of its factor gates (angles
+// from the sample's params / data rows), formed in double, rounded once.
 template <typename T>
-__global__ void k_prepare(const DGate *gates, const double2 *fixed, const DSlot *slots, int nslots,
-                          const double *params, int64_t pstride, const double *data, int64_t dstride,
-                          cx<T> *mats, int64_t block) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t b = blockIdx.y;
-    if (s >= nslots) return;
-    const DSlot sl = slots[s];
-    cx<T> *out = mats + b * block + sl.off;
+__device__ void prepare_slot(const DGate *gates, const double2 *fixed, const DSlot &sl, const double *prow,
+                             const double *drow, cx<T> *out) {
     const int dim = sl.dim;
     if (dim > 4) {  // a single dense factor of 3..5 qubits
         const DGate g = gates[sl.f[0]];
@@ -100,8 +96,8 @@ __global__ void k_prepare(const DGate *gates, const double2 *fixed, const DSlot 
     for (int f = 0; f < sl.nf; ++f) {
         const DGate g = gates[sl.f[f]];
         double v = 1.0;
-        if (g.src == SRC_PARAM) v = params[b * pstride + g.idx];
-        else if (g.src == SRC_DATA) v = data[b * dstride + g.idx];
+        if (g.src == SRC_PARAM) v = prow[g.idx];
+        else if (g.src == SRC_DATA) v = drow[g.idx];
         gate_matrix(g, g.scale * v, fixed, F);
         for (int r = 0; r < dim; ++r)          // P = F * M  (F acts after M)
             for (int c = 0; c < dim; ++c) {
@@ -121,6 +117,30 @@ __global__ void k_prepare(const DGate *gates, const double2 *fixed, const DSlot 
             if (sl.dagger) e.y = -e.y;
             out[r * dim + c] = cx<T>{(T)e.x, (T)e.y};
         }
+}
+
+template <typename T>
+__global__ void k_prepare(const DGate *gates, const double2 *fixed, const DSlot *slots, int nslots,
+                          const double *params, int64_t pstride, const double *data, int64_t dstride,
+                          cx<T> *mats, int64_t block) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = blockIdx.y;
+    if (s >= nslots) return;
+    const DSlot sl = slots[s];
+    prepare_slot<T>(gates, fixed, sl, params ? params + b * pstride : nullptr, data ? data + b * dstride : nullptr,
+                    mats + b * block + sl.off);
+}
+
+// Uneven batches: the slots of every circuit in one launch (blockIdx.y =
+// circuit entry); matrices at ws + mats_off, parameters at params + par_off.
+template <typename T>
+__global__ void k_prepare_multi(const MPrep *ents, const double *params, char *ws) {
+    const MPrep E = ents[blockIdx.y];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= E.nslots) return;
+    const DSlot sl = E.slots[s];
+    prepare_slot<T>(E.gates, E.fixed, sl, params ? params + E.par_off : nullptr, nullptr,
+                    (cx<T> *)(ws + E.mats_off) + sl.off);
 }
 
 // One dense block per workgroup, one column per thread: the column starts
@@ -278,6 +298,38 @@ __global__ __launch_bounds__(256) void k_init_product_tab(cx<T> *st, int n, cons
             const double2 a = mul(q, tab[r]);
             pb[(r << 8) + t] = cx<T>{(T)a.x, (T)a.y};
         }
+    }
+}
+
+// Uneven batches: every circuit's start state in one launch (blockIdx.y =
+// circuit entry): the folded product state (as k_init_product) or |0..0>.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_multi(cx<T> *st, const char *ws, const MInit *ents) {
+    __shared__ double2 u[64][2];
+    const MInit E = ents[blockIdx.y];
+    const int n = E.n;
+    const int64_t N = int64_t(1) << n;
+    if (blockIdx.x * (int64_t)blockDim.x >= N) return;   // block-uniform
+    if (threadIdx.x < n) {
+        const int64_t off = E.has_fold ? E.fold[threadIdx.x] : -1;
+        if (off < 0) {
+            u[threadIdx.x][0] = double2{1.0, 0.0};
+            u[threadIdx.x][1] = double2{0.0, 0.0};
+        } else {
+            const cx<T> *m = (const cx<T> *)(ws + E.mats_off) + off;
+            u[threadIdx.x][0] = double2{(double)m[0].x, (double)m[0].y};
+            u[threadIdx.x][1] = double2{(double)m[2].x, (double)m[2].y};
+        }
+    }
+    __syncthreads();
+    cx<T> *p = st + E.st_off;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        double2 acc{1.0, 0.0};
+        for (int k = 0; k < n; ++k) {
+            const double2 f = u[k][(j >> k) & 1];
+            acc = double2{acc.x * f.x - acc.y * f.y, acc.x * f.y + acc.y * f.x};
+        }
+        p[j] = cx<T>{(T)acc.x, (T)acc.y};
     }
 }
 
@@ -649,7 +701,7 @@ constexpr int EXP_TM = 32;
 // amplitude is loaded once per group.
 template <typename T, bool DIAG>
 __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t x, cptr<DTerm> terms, int c0,
-                                             int nt, double *row, int eb, double (*red)[2 * EXP_TM]) {
+                                             int nt, double *row, int eb, double (*red)[2 * EXP_TM], int64_t blk) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint64_t z[EXP_TM];
     double ar[EXP_TM], ai[EXP_TM];
@@ -660,7 +712,7 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
         ai[t] = 0.0;
     }
     if (DIAG) {
-        for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)eb * blockDim.x) {
+        for (int64_t j = blk * blockDim.x + threadIdx.x; j < N; j += (int64_t)eb * blockDim.x) {
             const cx<T> a = p[j];
             const double pr = (double)(a.x * a.x + a.y * a.y);
 #pragma unroll
@@ -677,7 +729,7 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
         bool odd[EXP_TM];
 #pragma unroll
         for (int t = 0; t < EXP_TM; ++t) odd[t] = t < nt && (__popcll(x & z[t]) & 1);
-        for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < (N >> 1); k += (int64_t)eb * blockDim.x) {
+        for (int64_t k = blk * blockDim.x + threadIdx.x; k < (N >> 1); k += (int64_t)eb * blockDim.x) {
             const int64_t j = ((k & ~lo) << 1) | (k & lo);
             const cx<T> a = p[j];
             const cx<T> o = p[j ^ (int64_t)x];
@@ -726,9 +778,68 @@ __global__ __launch_bounds__(256) void k_expval_part(const cx<T> *st, int n, con
         const int t0 = gp[g].t0, t1 = gp[g].t1;
         for (int c0 = t0; c0 < t1; c0 += EXP_TM) {
             const int nt = (t1 - c0) < EXP_TM ? (t1 - c0) : EXP_TM;
-            if (x == 0) expval_chunk<T, true>(p, N, x, tp, c0, nt, row, eb, red);
-            else expval_chunk<T, false>(p, N, x, tp, c0, nt, row, eb, red);
+            if (x == 0) expval_chunk<T, true>(p, N, x, tp, c0, nt, row, eb, red, blockIdx.x);
+            else expval_chunk<T, false>(p, N, x, tp, c0, nt, row, eb, red, blockIdx.x);
         }
+    }
+}
+
+// multi-plan entries: work unit u belongs to the entry e with
+// unit_begin[e] <= u < unit_begin[e + 1] (binary search; entries ascending)
+template <typename E>
+__device__ __forceinline__ int find_unit(const E *ents, int nent, int64_t u) {
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ents[mid].unit_begin <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Uneven batches: the expectation partial sums of every circuit in one
+// launch, block u doing chunk u - unit_begin of its circuit's eb chunks,
+// every X-mask group of the circuit (as k_expval_part).
+template <typename T>
+__global__ __launch_bounds__(256) void k_expval_multi(const cx<T> *st, char *ws, const MExp *ents, int nent) {
+    __shared__ double red[4][2 * EXP_TM];
+    const int e = find_unit(ents, nent, blockIdx.x);
+    const MExp E = ents[e];
+    const int64_t blk = blockIdx.x - E.unit_begin;
+    const int64_t N = int64_t(1) << E.n;
+    const cx<T> *p = st + E.st_off;
+    const cptr<DGroup> gp = to_const(E.groups);
+    const cptr<DTerm> tp = to_const(E.terms);
+    double *row = (double *)(ws + E.part_off) + blk * (int64_t)E.nterms * 2;
+    for (int g = 0; g < E.ngroups; ++g) {
+        const uint64_t x = gp[g].xmask;
+        const int t0 = gp[g].t0, t1 = gp[g].t1;
+        for (int c0 = t0; c0 < t1; c0 += EXP_TM) {
+            const int nt = (t1 - c0) < EXP_TM ? (t1 - c0) : EXP_TM;
+            if (x == 0) expval_chunk<T, true>(p, N, x, tp, c0, nt, row, E.eb, red, blk);
+            else expval_chunk<T, false>(p, N, x, tp, c0, nt, row, E.eb, red, blk);
+        }
+    }
+}
+
+// out[out_off + o] = sum over the terms of observable o of Re(w_t S_t), the
+// chunks summed in order (one block per circuit, a thread per observable)
+__global__ void k_expval_final_multi(const char *ws, const MExp *ents, double *out) {
+    const MExp E = ents[blockIdx.x];
+    const double *part = (const double *)(ws + E.part_off);
+    for (int o = threadIdx.x; o < E.nobs; o += blockDim.x) {
+        double v = 0.0;
+        for (int t = 0; t < E.nterms; ++t) {
+            const DTerm tm = E.terms[t];
+            if (tm.obs != o) continue;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < E.eb; ++k) {
+                sr += part[((int64_t)k * E.nterms + t) * 2];
+                si += part[((int64_t)k * E.nterms + t) * 2 + 1];
+            }
+            v += tm.wr * sr - tm.wi * si;
+        }
+        out[E.out_off + o] = v;
     }
 }
 
@@ -862,6 +973,69 @@ __global__ __launch_bounds__(256) void k_lambda(const cx<T> *psi, cx<T> *lam, in
         }
         lam[i] = cx<T>{(T)ar, (T)ai};
     }
+}
+
+// Uneven batches: every circuit's adjoint seed in one launch; amplitude i of
+// the concatenated circuits belongs to the entry whose [amp_begin, amp_begin
+// + 2^n) holds it; weights at gout + out_off.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lambda_multi(const cx<T> *st, char *ws, const MExp *ents, int nent,
+                                                      int64_t total, const double *gout) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nent - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ents[mid].amp_begin <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const MExp &E = ents[lo];
+        const int64_t j = i - E.amp_begin;
+        const cx<T> *p = st + E.st_off;
+        const double *go = gout + E.out_off;
+        double ar = 0.0, ai = 0.0;
+        for (int g = 0; g < E.ngroups; ++g) {
+            const uint64_t x = E.groups[g].xmask;
+            const int64_t jx = j ^ (int64_t)x;
+            double dr = 0.0, di = 0.0;
+            for (int t = E.groups[g].t0; t < E.groups[g].t1; ++t) {
+                const DTerm tm = E.terms[t];
+                const double w = go[tm.obs];
+                const bool neg = __popcll((uint64_t)jx & tm.zmask) & 1;
+                dr += neg ? -w * tm.wr : w * tm.wr;
+                di += neg ? -w * tm.wi : w * tm.wi;
+            }
+            const cx<T> o = p[jx];
+            ar += dr * (double)o.x - di * (double)o.y;
+            ai += dr * (double)o.y + di * (double)o.x;
+        }
+        ((cx<T> *)(ws + E.lam_off))[j] = cx<T>{(T)ar, (T)ai};
+    }
+}
+
+// Uneven batches: every circuit's parameter gradients in one launch, one
+// wave per output (unit u = packed parameter index): the wave's lanes take
+// the per-wave partial sums w = lane, lane + 64, ... of each gradient slot of
+// the parameter, weighted by its chain factor, then a fixed shuffle tree
+// adds the lanes (deterministic).
+__global__ __launch_bounds__(256) void k_grad_final_multi(const char *ws, const MGrad *ents, int nent, int64_t total,
+                                                          double *out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t u = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (u >= total) return;   // wave-uniform
+    const int e = find_unit(ents, nent, u);
+    const MGrad E = ents[e];
+    const int64_t p = u - E.unit_begin;
+    const double *part = (const double *)(ws + E.part_off);
+    double s = 0.0;
+    for (int64_t k = E.poff[p]; k < E.poff[p + 1]; ++k) {
+        const int g = E.pg[k];
+        double t = 0.0;
+        for (int w = lane; w < E.wps; w += 64) t += part[(int64_t)w * E.ngrad + g];
+        s += E.pf[k] * t;
+    }
+    s = wave_sum(s);
+    if (lane == 0) out[E.par_off + p] = s;
 }
 
 }  // namespace
@@ -1140,6 +1314,60 @@ hipError_t launch_grad_final(const double *partial, int64_t batch, int32_t wps, 
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_final, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, partial, batch, wps, ngrad,
                        csr_off, csr_g, csr_f, nout, per_sample, out);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_prepare_multi(int dbl, const MPrep *ents, int32_t nent, int32_t max_slots, const double *params,
+                                void *ws, hipStream_t s) {
+    if (nent <= 0 || max_slots <= 0) return hipSuccess;
+    dim3 grid((unsigned)((max_slots + 63) / 64), (unsigned)nent);
+    if (dbl) hipLaunchKernelGGL(k_prepare_multi<double>, grid, dim3(64), 0, s, ents, params, (char *)ws);
+    else hipLaunchKernelGGL(k_prepare_multi<float>, grid, dim3(64), 0, s, ents, params, (char *)ws);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_init_multi(int dbl, void *st, const void *ws, const MInit *ents, int32_t nent, int32_t max_n,
+                             hipStream_t s) {
+    if (nent <= 0) return hipSuccess;
+    const int64_t N = int64_t(1) << max_n;
+    dim3 grid(grid_for(N, 256, 4096), (unsigned)nent);
+    if (dbl) hipLaunchKernelGGL(k_init_multi<double>, grid, dim3(256), 0, s, (C128 *)st, (const char *)ws, ents);
+    else hipLaunchKernelGGL(k_init_multi<float>, grid, dim3(256), 0, s, (C64 *)st, (const char *)ws, ents);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_expval_multi(int dbl, const void *st, void *ws, const MExp *ents, int32_t nent, int64_t units,
+                               double *out, hipStream_t s) {
+    if (nent <= 0) return hipSuccess;
+    if (dbl)
+        hipLaunchKernelGGL(k_expval_multi<double>, dim3((unsigned)units), dim3(256), 0, s, (const C128 *)st, (char *)ws,
+                           ents, nent);
+    else
+        hipLaunchKernelGGL(k_expval_multi<float>, dim3((unsigned)units), dim3(256), 0, s, (const C64 *)st, (char *)ws,
+                           ents, nent);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_expval_final_multi, dim3((unsigned)nent), dim3(64), 0, s, (const char *)ws, ents, out);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_lambda_multi(int dbl, const void *st, void *ws, const MExp *ents, int32_t nent, int64_t total,
+                               const double *gout, hipStream_t s) {
+    if (nent <= 0) return hipSuccess;
+    if (dbl)
+        hipLaunchKernelGGL(k_lambda_multi<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C128 *)st,
+                           (char *)ws, ents, nent, total, gout);
+    else
+        hipLaunchKernelGGL(k_lambda_multi<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C64 *)st,
+                           (char *)ws, ents, nent, total, gout);
+    DQ_LAUNCH_RET;
+}
+
+hipError_t launch_grad_final_multi(const void *ws, const MGrad *ents, int32_t nent, int64_t total, double *out,
+                                   hipStream_t s) {
+    if (nent <= 0 || total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_final_multi, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, (const char *)ws, ents,
+                       nent, total, out);
     DQ_LAUNCH_RET;
 }
 

@@ -2107,6 +2107,10 @@ dq_status dq_profile_read(dq_plan plan, dq_profile *out, int32_t reset) try {
 // ================================================================ uneven batches
 }  // extern "C"
 
+namespace {
+constexpr int64_t kMultiWps = 256;   // adjoint waves per circuit in an uneven batch (at most)
+}
+
 struct dq_multi_s {
     int dbl = 0;
     int R_fwd = 0, R_adj = 0;
@@ -2124,10 +2128,19 @@ struct dq_multi_s {
     std::vector<std::vector<int>> fwd_c, adj_c;       // circuit of each entry
     std::vector<int64_t> fwd_units, adj_units;
     std::vector<int32_t> adj_maxnls;
+    std::vector<int32_t> wps;                          // adjoint waves per circuit
+    std::vector<int> bc;                               // the batched circuits, in order
     std::mutex mu;
     struct Dev {
         void *blob = nullptr;
         std::vector<MultiEntry *> fwd, adj;
+        // the per-circuit steps around the tile passes, one launch each
+        MPrep *prep_fwd = nullptr, *prep_adj = nullptr;
+        MInit *init = nullptr;
+        MExp *exp = nullptr;
+        MGrad *grad = nullptr;
+        int32_t max_slots_fwd = 0, max_slots_adj = 0, max_n = 0;
+        int64_t exp_units = 0, lam_total = 0, grad_total = 0;
     };
     std::map<int, Dev> dev;
 };
@@ -2186,15 +2199,89 @@ dq_status ensure_multi(dq_multi_s &m, dq_multi_s::Dev **out) {
         astart.push_back(all.size());
         resolve(m.adj[k], m.adj_c[k]);
     }
+    // the batched circuits' per-circuit steps, resolved for this device
     dq_multi_s::Dev D;
-    DQ_HIP(hipMalloc(&D.blob, std::max<size_t>(all.size(), 1) * sizeof(MultiEntry)));
-    hipError_t e = hipMemcpy(D.blob, all.data(), all.size() * sizeof(MultiEntry), hipMemcpyHostToDevice);
+    std::vector<MPrep> pf, pa;
+    std::vector<MInit> in;
+    std::vector<MExp> ex;
+    std::vector<MGrad> gr;
+    for (int c : m.bc) {
+        dq_plan p = m.plans[c];
+        DevData &d = p->dev[dev];
+        const WsLayout &L = m.lay[c];
+        const size_t wo = m.ws_off[c];
+        const Program &f = p->has_fold ? p->fwd_fold : p->fwd_full;
+        MPrep P{};
+        P.gates = d.gates;
+        P.fixed = d.fixed;
+        P.par_off = m.par_off[c];
+        P.mats_off = (int64_t)(wo + L.mats);
+        P.slots = d.slots + f.slot_lo;
+        P.nslots = (int32_t)(f.slot_hi - f.slot_lo);
+        pf.push_back(P);
+        D.max_slots_fwd = std::max(D.max_slots_fwd, P.nslots);
+        P.slots = d.slots + p->adj.slot_lo;
+        P.nslots = (int32_t)(p->adj.slot_hi - p->adj.slot_lo);
+        pa.push_back(P);
+        D.max_slots_adj = std::max(D.max_slots_adj, P.nslots);
+        MInit I{};
+        I.st_off = m.st_off[c];
+        I.mats_off = (int64_t)(wo + L.mats);
+        I.fold = d.fold;
+        I.n = p->n;
+        I.has_fold = p->has_fold ? 1 : 0;
+        in.push_back(I);
+        D.max_n = std::max(D.max_n, p->n);
+        const DGroup *g = nullptr;
+        const DTerm *t = nullptr;
+        dq_status st = ensure_obs(*m.obs[c], &g, &t);
+        if (st != DQ_OK) return st;
+        MExp X{};
+        X.st_off = m.st_off[c];
+        X.lam_off = (int64_t)(wo + L.lam);
+        X.part_off = (int64_t)(wo + L.expv);
+        X.unit_begin = D.exp_units;
+        X.amp_begin = D.lam_total;
+        X.out_off = m.out_off[c];
+        X.groups = g;
+        X.terms = t;
+        X.n = p->n;
+        X.ngroups = (int32_t)m.obs[c]->groups.size();
+        X.nterms = (int32_t)m.obs[c]->terms.size();
+        X.nobs = m.obs[c]->nobs;
+        X.eb = (int32_t)expval_blocks(p->n, 1);
+        ex.push_back(X);
+        D.exp_units += X.eb;
+        D.lam_total += int64_t(1) << p->n;
+        MGrad G{};
+        G.part_off = (int64_t)(wo + L.part);
+        G.par_off = m.par_off[c];
+        G.unit_begin = D.grad_total;
+        G.poff = d.poff;
+        G.pg = d.pg;
+        G.pf = d.pf;
+        G.wps = m.wps[c];
+        G.ngrad = p->ngrad;
+        gr.push_back(G);
+        D.grad_total += p->nparams;
+    }
+    std::vector<char> blob;
+    const size_t o_all = put(blob, all), o_pf = put(blob, pf), o_pa = put(blob, pa), o_in = put(blob, in),
+                 o_ex = put(blob, ex), o_gr = put(blob, gr);
+    DQ_HIP(hipMalloc(&D.blob, std::max<size_t>(blob.size(), 1)));
+    hipError_t e = hipMemcpy(D.blob, blob.data(), blob.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(D.blob);
         return fail(DQ_ERR_HIP, "multi upload: %s", hipGetErrorString(e));
     }
-    for (size_t k : fstart) D.fwd.push_back((MultiEntry *)D.blob + k);
-    for (size_t k : astart) D.adj.push_back((MultiEntry *)D.blob + k);
+    char *bb = (char *)D.blob;
+    for (size_t k : fstart) D.fwd.push_back((MultiEntry *)(bb + o_all) + k);
+    for (size_t k : astart) D.adj.push_back((MultiEntry *)(bb + o_all) + k);
+    D.prep_fwd = (MPrep *)(bb + o_pf);
+    D.prep_adj = (MPrep *)(bb + o_pa);
+    D.init = (MInit *)(bb + o_in);
+    D.exp = (MExp *)(bb + o_ex);
+    D.grad = (MGrad *)(bb + o_gr);
     *out = &(m.dev[dev] = D);
     return DQ_OK;
 }
@@ -2251,6 +2338,14 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
                              tile_only(p->adj, m->R_adj) && multi_fwd_has(m->dbl, m->R_fwd) &&
                              multi_adj_has(m->dbl, m->R_adj));
     }
+    // adjoint waves per circuit: each wave walks tiles w, w + wps, ... and
+    // leaves one row of partial gradient sums, which the final reduction
+    // adds; capped, so that the rows stay few while the waves of all
+    // circuits together still fill the device
+    for (int c = 0; c < nplans; ++c) {
+        m->wps.push_back((int32_t)std::min<int64_t>(grad_waves(*m->plans[c], 1), kMultiWps));
+        if (m->batched[c]) m->bc.push_back(c);
+    }
     // depth tables
     const double tot_bytes = (double)m->st_total * (double)amp;   // all circuits' states
     for (int pass = 0; pass < 2; ++pass) {
@@ -2277,7 +2372,7 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
                 E.ngrad = p->ngrad;
                 E.nt = tot_bytes * (pass ? 2 : 1) > kStreamBytes ? 1 : 0;
                 const int64_t tiles = int64_t(1) << (p->n - 6 - (pass ? m->R_adj : m->R_fwd));
-                E.wps = (int32_t)(pass ? grad_waves(*p, 1) : 1);
+                E.wps = pass ? m->wps[c] : 1;
                 E.unit_begin = units[d];
                 units[d] += pass ? E.wps : tiles;
                 if (pass) m->adj_maxnls[d] = std::max<int32_t>(m->adj_maxnls[d], E.nls);
@@ -2345,27 +2440,20 @@ dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *w
     const size_t amp = m->dbl ? 16 : 8;
     char *w = (char *)ws;
     for (size_t c = 0; c < m->plans.size(); ++c) {
-        dq_plan p = m->plans[c];
+        if (m->batched[c]) continue;
         void *sc = (char *)states + m->st_off[c] * amp;
         const double *pc = params ? params + m->par_off[c] : nullptr;
-        if (!m->batched[c]) {
-            if ((st = dq_apply_circuit(p, sc, 1, pc, 0, nullptr, 0, 1, w + m->ws_off[c], m->lay[c].total, stream)) != DQ_OK)
-                return st;
-            continue;
-        }
-        DevData &d = p->dev.at([&] { int dv = 0; (void)hipGetDevice(&dv); return dv; }());
-        const Program &prog = p->has_fold ? p->fwd_fold : p->fwd_full;
-        void *mats = w + m->ws_off[c] + m->lay[c].mats;
-        hipError_t e = launch_prepare(p->dbl, d.gates, d.fixed, d.slots + prog.slot_lo, (int32_t)(prog.slot_hi - prog.slot_lo),
-                                      pc, 0, nullptr, 0, mats, p->block, 1, s);
-        if (e == hipSuccess)
-            e = p->has_fold ? launch_init_product(p->dbl, sc, p->n, 1, mats, 0, d.fold, s)
-                            : launch_init_zero(p->dbl, sc, p->n, 1, s);
-        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi init: %s", hipGetErrorString(e));
+        if ((st = dq_apply_circuit(m->plans[c], sc, 1, pc, 0, nullptr, 0, 1, w + m->ws_off[c], m->lay[c].total,
+                                   stream)) != DQ_OK)
+            return st;
     }
+    // the batched circuits: matrices, start states, then one tile launch per depth
+    const int32_t nb = (int32_t)m->bc.size();
+    hipError_t e = launch_prepare_multi(m->dbl, D->prep_fwd, nb, D->max_slots_fwd, params, ws, s);
+    if (e == hipSuccess) e = launch_init_multi(m->dbl, states, ws, D->init, nb, D->max_n, s);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi init: %s", hipGetErrorString(e));
     for (size_t k = 0; k < m->fwd.size(); ++k) {
-        hipError_t e = launch_tile_fwd_multi(m->dbl, m->R_fwd, states, ws, D->fwd[k], (int32_t)m->fwd[k].size(),
-                                             m->fwd_units[k], s);
+        e = launch_tile_fwd_multi(m->dbl, m->R_fwd, states, ws, D->fwd[k], (int32_t)m->fwd[k].size(), m->fwd_units[k], s);
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi tile pass: %s", hipGetErrorString(e));
     }
     return ok();
@@ -2374,12 +2462,19 @@ dq_status dq_multi_apply(dq_multi m, void *states, const double *params, void *w
 dq_status dq_multi_expval(dq_multi m, const void *states, double *out, void *ws, size_t ws_bytes, void *stream) try {
     if (!m || !states || !out) return fail(DQ_ERR_INVALID_ARG, "NULL argument");
     if (!ws || ws_bytes < m->ws_total) return fail(DQ_ERR_WORKSPACE, "workspace of %zu bytes needed", m->ws_total);
+    dq_multi_s::Dev *D = nullptr;
+    dq_status st = ensure_multi(*m, &D);
+    if (st != DQ_OK) return st;
     const size_t amp = m->dbl ? 16 : 8;
     for (size_t c = 0; c < m->plans.size(); ++c) {
-        dq_status st = dq_expval(m->plans[c], m->obs[c], (const char *)states + m->st_off[c] * amp, 1,
-                                 out + m->out_off[c], (char *)ws + m->ws_off[c], m->lay[c].total, stream);
-        if (st != DQ_OK) return st;
+        if (m->batched[c]) continue;
+        if ((st = dq_expval(m->plans[c], m->obs[c], (const char *)states + m->st_off[c] * amp, 1, out + m->out_off[c],
+                            (char *)ws + m->ws_off[c], m->lay[c].total, stream)) != DQ_OK)
+            return st;
     }
+    const hipError_t e = launch_expval_multi(m->dbl, states, ws, D->exp, (int32_t)m->bc.size(), D->exp_units, out,
+                                             (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi expval: %s", hipGetErrorString(e));
     return ok();
 } DQ_CATCH
 
@@ -2394,48 +2489,27 @@ dq_status dq_multi_adjoint_grad(dq_multi m, void *states, const double *params, 
     hipStream_t s = (hipStream_t)stream;
     const size_t amp = m->dbl ? 16 : 8;
     char *w = (char *)ws;
-    int dv = 0;
-    DQ_HIP(hipGetDevice(&dv));
     for (size_t c = 0; c < m->plans.size(); ++c) {
+        if (m->batched[c]) continue;
         dq_plan p = m->plans[c];
         void *sc = (char *)states + m->st_off[c] * amp;
         const double *pc = params ? params + m->par_off[c] : nullptr;
         double *gc = grad_params ? grad_params + m->par_off[c] : nullptr;
-        if (!m->batched[c]) {
-            if ((st = dq_adjoint_grad(p, m->obs[c], sc, 1, pc, 0, nullptr, 0, grad_out + m->out_off[c], gc, nullptr, 0,
-                                      w + m->ws_off[c], m->lay[c].total, stream)) != DQ_OK)
-                return st;
-            continue;
-        }
-        DevData &d = p->dev.at(dv);
-        const DGroup *g = nullptr;
-        const DTerm *t = nullptr;
-        if ((st = ensure_obs(*m->obs[c], &g, &t)) != DQ_OK) return st;
-        void *mats = w + m->ws_off[c] + m->lay[c].mats;
-        void *lam = w + m->ws_off[c] + m->lay[c].lam;
-        hipError_t e = launch_prepare(p->dbl, d.gates, d.fixed, d.slots + p->adj.slot_lo,
-                                      (int32_t)(p->adj.slot_hi - p->adj.slot_lo), pc, 0, nullptr, 0, mats, p->block, 1, s);
-        int32_t dt0, dt1;
-        zdiag_range(*p, *m->obs[c], dt0, dt1);
-        if (e == hipSuccess)
-            e = launch_lambda(p->dbl, sc, lam, p->n, 1, g, (int32_t)m->obs[c]->groups.size(), t, grad_out + m->out_off[c],
-                              m->obs[c]->nobs, dt0, dt1, s);
-        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi adjoint seed: %s", hipGetErrorString(e));
+        if ((st = dq_adjoint_grad(p, m->obs[c], sc, 1, pc, 0, nullptr, 0, grad_out + m->out_off[c], gc, nullptr, 0,
+                                  w + m->ws_off[c], m->lay[c].total, stream)) != DQ_OK)
+            return st;
     }
+    const int32_t nb = (int32_t)m->bc.size();
+    hipError_t e = launch_prepare_multi(m->dbl, D->prep_adj, nb, D->max_slots_adj, params, ws, s);
+    if (e == hipSuccess) e = launch_lambda_multi(m->dbl, states, ws, D->exp, nb, D->lam_total, grad_out, s);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi adjoint seed: %s", hipGetErrorString(e));
     for (size_t k = 0; k < m->adj.size(); ++k) {
-        hipError_t e = launch_tile_adj_multi(m->dbl, m->R_adj, states, ws, D->adj[k], (int32_t)m->adj[k].size(),
-                                             m->adj_units[k], m->adj_maxnls[k], s);
+        e = launch_tile_adj_multi(m->dbl, m->R_adj, states, ws, D->adj[k], (int32_t)m->adj[k].size(), m->adj_units[k],
+                                  m->adj_maxnls[k], s);
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi adjoint pass: %s", hipGetErrorString(e));
     }
-    for (size_t c = 0; c < m->plans.size(); ++c) {
-        dq_plan p = m->plans[c];
-        if (!m->batched[c] || p->nparams == 0) continue;
-        DevData &d = p->dev.at(dv);
-        double *partial = (double *)(w + m->ws_off[c] + m->lay[c].part);
-        hipError_t e = launch_grad_final(partial, 1, (int32_t)grad_waves(*p, 1), p->ngrad, d.poff, d.pg, d.pf, p->nparams,
-                                         0, grad_params + m->par_off[c], s);
-        if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi grad reduce: %s", hipGetErrorString(e));
-    }
+    e = launch_grad_final_multi(ws, D->grad, nb, D->grad_total, grad_params, s);
+    if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi grad reduce: %s", hipGetErrorString(e));
     return ok();
 } DQ_CATCH
 

@@ -337,6 +337,78 @@ def cpu_baseline_uneven(mw):
             "sample_seconds": wall}
 
 
+def bench_hessian(args):
+    """The Hessian of the paper's second gradient benchmark (section 3.1) on
+    the hardware-efficient ansatz family of the 32-qubit workload (RY, RZ on
+    every wire, CNOT ring; observable sum_i Z_i Z_{i+1}) at --hess-qubits
+    qubits and --hess-layers layers, complex64: one batched forward and
+    adjoint sweep over the 2K parameter-shifted circuits per Hessian."""
+    import numpy as np
+    import torch
+    import paper_2512_18995_amd as dq
+    import workloads as W
+    dev = "cuda:0"
+    n, L = args.hess_qubits, args.hess_layers
+    wl = W.config(5, n=n, layers=L)
+    c = wl.circuit
+    plan = dq.Plan(c, "c64", jit=True)
+    obs = dq.Observable(n, wl.observables)
+    p = torch.as_tensor(wl.params, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    for _ in range(max(args.warmup, 1)):
+        H = dq.hessian(plan, obs, p)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        H = dq.hessian(plan, obs, p)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    Hn = H.cpu().numpy()
+    P = c.n_params
+    # plain path: one forward with one launch per gate, times the forward
+    # evaluations of a double parameter shift (4 per pair of angles, pairs
+    # counted once: 2 P (P + 1))
+    pp = dq.Plan(c, "c64", fusion=False)
+    st = pp.state(1, dev)
+    pws = pp.workspace(1, False, 0, obs, dev)
+    dq.apply_circuit(pp, st, p, None, ws=pws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dq.apply_circuit(pp, st, p, None, ws=pws)
+    dq.expval(pp, obs, st, ws=pws)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t1
+    evals = 2 * P * (P + 1)
+    plain = {"value": 1.0 / (t_fwd * evals), "unit": "hessians/s",
+             "sample": "one plain-path forward + expectation (%.4f s) x %d evaluations (double parameter shift, "
+                       "4 per unordered pair of angles)" % (t_fwd, evals)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.lib()
+        t2 = time.perf_counter()
+        oracle.forward(c, wl.params, None, wl.observables, 1, threads=1)
+        t_o = time.perf_counter() - t2
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+        cpu = {"value": cores / (t_o * evals), "unit": "hessians/s", "cores": cores, "kind": "oracle",
+               "sample": "one oracle forward + expectation at full size (%.2f s on one thread) x %d evaluations "
+                         "of the double parameter shift, spread over %d threads (evaluations independent)" % (
+                             t_o, evals, cores),
+               "sample_seconds": t_o}
+    out = {"metric": METRIC, "value": 1.0 / dt, "unit": "hessians/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+           "config": {"workload": "hessian-hea-n%d-L%d-c64" % (n, L), "qubits": n, "layers": L, "params": P,
+                      "shifted_circuits": 2 * P, "parallelism": "none (one GPU)"},
+           "first_call_s": first, "plain_path": plain, "speedup_vs_plain": (1.0 / dt) / plain["value"],
+           "cpu_baseline": cpu,
+           "checks": {"symmetry": float(np.max(np.abs(Hn - Hn.T)) / max(np.max(np.abs(Hn)), 1e-300)),
+                      "frobenius": float(np.linalg.norm(Hn))},
+           "roofline": None, "source_hash": kernel_source_hash()}
+    print(json.dumps(out), flush=True)
+
+
 def bench_qft(args):
     """The quantum Fourier transform of the paper's distributed-QFT listing
     (per wire a Hadamard and controlled phases, then the wire-reversing
@@ -449,7 +521,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg5", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "qft"])
+    ap.add_argument("--workload", default="cfg5", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "qft", "hessian"])
+    ap.add_argument("--hess-qubits", type=int, default=20)
+    ap.add_argument("--hess-layers", type=int, default=2)
     ap.add_argument("--qft-qubits", type=int, default=32)
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--adj-tile-bits", type=int, default=0)
@@ -462,6 +536,11 @@ def main():
                          "compiled for every single-plan workload (the compiles fall in the untimed first "
                          "warm-up step, reported as first_step_s, and are cached on disk); the multi-circuit "
                          "workload always runs interpreted passes")
+    ap.add_argument("--arith", choices=["auto", "32", "64"], default="auto",
+                    help="arithmetic of the complex64 tile passes: 32 (float32) or 64 (float64 on complex64 "
+                         "storage, one rounding per amplitude per pass); auto: 64 for the 32-qubit workload, "
+                         "whose 1920 gates take float32 arithmetic beyond the 1e-5 gradient target "
+                         "(4.2e-5 normwise against complex128; 1.7e-7 with float64), 32 elsewhere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true",
@@ -497,13 +576,18 @@ def main():
     if args.workload == "qft":
         bench_qft(args)
         return
+    if args.workload == "hessian":
+        bench_hessian(args)
+        return
     cid = int(args.workload[3:])
     wl = W.config(cid)
     c = wl.circuit
     B = wl.batch
     jit = args.passes != "interpreted"
+    arith64 = wl.dtype == "c64" and jit and (args.arith == "64" or (args.arith == "auto" and cid == 5))
     plan = dq.Plan(c, wl.dtype, tile_bits=args.tile_bits, dense_fuse=args.dense_fuse, jit=jit,
-                   adj_tile_bits=args.adj_tile_bits, low_bits=args.low_bits, layout=args.layout)
+                   adj_tile_bits=args.adj_tile_bits, low_bits=args.low_bits, layout=args.layout,
+                   arith64=arith64)
     obs = dq.Observable(c.n, wl.observables)
     params = torch.as_tensor(wl.params, dtype=torch.float64, device=dev)
     data = None if wl.data is None else torch.as_tensor(wl.data, dtype=torch.float64, device=dev)
@@ -650,6 +734,8 @@ def main():
                  "folded_gates": st["folded_gates"], "tile_bits": st["tile_bits"],
                  "adj_tile_bits": st["adj_tile_bits"], "layout_swaps": st["layout_swaps"],
                  "passes": "compiled" if jit else "interpreted",
+                 "arithmetic": "float64 on complex64 storage" if arith64 else (
+                     "float32" if wl.dtype == "c64" else "float64"),
                  "compiled_kernels": len(plan.jit_sources()), "first_step_s": first_step_s},
         "checks": checks,
         "errors": errors,

@@ -150,6 +150,15 @@ typedef struct {
                              undone by swaps appended to the circuit, so states keep the
                              canonical order) and keep the plan with the fewest sweeps;
                              1: canonical bit order only */
+    int32_t arith64;      /* 0 (default): tile passes compute in the state's precision;
+                             1 (complex64 plans with jit = 1, fusion = 1, dense_fuse = 0 only;
+                             else DQ_ERR_UNSUPPORTED): complex64 states swept with float64
+                             arithmetic and float64 gate matrices, each amplitude rounded to
+                             complex64 once per pass (about 8x smaller gradient error against
+                             complex128 on deep circuits); tiles hold one register bit less
+                             (as for complex128), so passes are more numerous; dense UNITARY
+                             gates of two or more wires (which run as per-gate sweeps) are not
+                             supported in such plans (DQ_ERR_UNSUPPORTED) */
 } dq_options;
 
 typedef struct dq_plan_s *dq_plan;

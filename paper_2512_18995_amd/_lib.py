@@ -42,7 +42,8 @@ class DqPauliTerm(ctypes.Structure):
 
 class DqOptions(ctypes.Structure):
     _fields_ = [("fusion", c_int32), ("tile_bits", c_int32), ("fold_init", c_int32), ("dense_fuse", c_int32),
-                ("jit", c_int32), ("adj_tile_bits", c_int32), ("low_bits", c_int32), ("layout", c_int32)]
+                ("jit", c_int32), ("adj_tile_bits", c_int32), ("low_bits", c_int32), ("layout", c_int32),
+                ("arith64", c_int32)]
 
 
 class DqPlanStats(ctypes.Structure):  # noqa: E302

@@ -140,7 +140,9 @@ hipError_t launch_prepare_blocks(int dbl, const DGate *gates, const void *fixed,
                                  hipStream_t s);
 hipError_t launch_init_zero(int dbl, void *st, int32_t n, int64_t batch, hipStream_t s);
 hipError_t launch_init_copy(int dbl, void *st, const void *init, int32_t n, int64_t batch, hipStream_t s);
-hipError_t launch_init_product(int dbl, void *st, int32_t n, int64_t batch, const void *mats,
+// mdbl: the folded matrices are complex128 (complex128 states, or complex64
+// states of a plan with float64 arithmetic)
+hipError_t launch_init_product(int dbl, int mdbl, void *st, int32_t n, int64_t batch, const void *mats,
                                int64_t mstride, const int64_t *fold_off, hipStream_t s);
 hipError_t launch_copy(int dbl, void *dst, const void *src, int64_t count, hipStream_t s);
 hipError_t launch_gate1(int dbl, void *st, int32_t n, int64_t batch, int32_t bit, const void *mats,

@@ -270,7 +270,10 @@ hipError_t jit_launch(hipFunction_t f, const std::string &name, const TileArgs &
         }
     }
     const int64_t tiles = a.batch << (a.n - 6 - a.R);
-    const int64_t cap = resident > 0 ? resident : 4096;
+    // four grid-stride waves per resident slot: the waves that wait for a
+    // slot fill the ramp-down of the ones before them (a 32-qubit forward
+    // pass: 14.26 against 14.61 ms with one wave per slot)
+    const int64_t cap = 4 * (resident > 0 ? resident : 4096);
     const unsigned g = (unsigned)(tiles < cap ? (tiles < 1 ? 1 : tiles) : cap);
     return hipModuleLaunchKernel(f, g, 1, 1, 64, 1, 1, 0, s, args, nullptr);
 }

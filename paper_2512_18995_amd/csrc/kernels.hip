@@ -227,8 +227,8 @@ __global__ void k_copy(cx<T> *dst, const cx<T> *src, int64_t count) {
 
 // amp_j = prod_s u_s[bit_s(j)], u_s = first column of the folded one-qubit
 // product on physical bit s (identity column (1, 0) where nothing is folded).
-template <typename T>
-__global__ __launch_bounds__(256) void k_init_product(cx<T> *st, int n, const cx<T> *mats, int64_t mstride,
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void k_init_product(cx<T> *st, int n, const cx<M> *mats, int64_t mstride,
                                                       const int64_t *fold_off) {
     __shared__ double2 u[64][2];
     const int64_t b = blockIdx.y;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_init_product(cx<T> *st, int n, const cx
             u[threadIdx.x][0] = double2{1.0, 0.0};
             u[threadIdx.x][1] = double2{0.0, 0.0};
         } else {
-            const cx<T> *m = mats + b * mstride + off;
+            const cx<M> *m = mats + b * mstride + off;
             u[threadIdx.x][0] = double2{(double)m[0].x, (double)m[0].y};
             u[threadIdx.x][1] = double2{(double)m[2].x, (double)m[2].y};
         }
@@ -260,8 +260,8 @@ __global__ __launch_bounds__(256) void k_init_product(cx<T> *st, int n, const cx
 // bits 16.. are fixed (one product per block), bits 8..15 index a 256-entry
 // product table in LDS and bits 0..7 are this thread's (one product per
 // thread), so each amplitude costs one complex multiply.
-template <typename T>
-__global__ __launch_bounds__(256) void k_init_product_tab(cx<T> *st, int n, const cx<T> *mats, int64_t mstride,
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void k_init_product_tab(cx<T> *st, int n, const cx<M> *mats, int64_t mstride,
                                                           const int64_t *fold_off) {
     __shared__ double2 u[64][2];
     __shared__ double2 tab[256];
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_init_product_tab(cx<T> *st, int n, cons
             u[t][0] = double2{1.0, 0.0};
             u[t][1] = double2{0.0, 0.0};
         } else {
-            const cx<T> *m = mats + b * mstride + off;
+            const cx<M> *m = mats + b * mstride + off;
             u[t][0] = double2{(double)m[0].x, (double)m[0].y};
             u[t][1] = double2{(double)m[2].x, (double)m[2].y};
         }
@@ -1167,27 +1167,27 @@ hipError_t launch_copy(int dbl, void *dst, const void *src, int64_t count, hipSt
     DQ_LAUNCH_RET;
 }
 
-hipError_t launch_init_product(int dbl, void *st, int32_t n, int64_t batch, const void *mats, int64_t mstride,
-                               const int64_t *fold_off, hipStream_t s) {
+template <typename T, typename M>
+static void init_product(void *st, int32_t n, int64_t batch, const void *mats, int64_t mstride,
+                         const int64_t *fold_off, hipStream_t s) {
     const int64_t N = int64_t(1) << n;
     if (n >= 16) {
         const int64_t nblk = N >> 16;
         dim3 grid((unsigned)(nblk < 4096 ? nblk : 4096), (unsigned)batch);
-        if (dbl)
-            hipLaunchKernelGGL(k_init_product_tab<double>, grid, dim3(256), 0, s, (C128 *)st, n, (const C128 *)mats,
-                               mstride, fold_off);
-        else
-            hipLaunchKernelGGL(k_init_product_tab<float>, grid, dim3(256), 0, s, (C64 *)st, n, (const C64 *)mats,
-                               mstride, fold_off);
-        DQ_LAUNCH_RET;
+        hipLaunchKernelGGL((k_init_product_tab<T, M>), grid, dim3(256), 0, s, (cx<T> *)st, n, (const cx<M> *)mats,
+                           mstride, fold_off);
+        return;
     }
     dim3 grid(grid_for(N, 256, 8192), (unsigned)batch);
-    if (dbl)
-        hipLaunchKernelGGL(k_init_product<double>, grid, dim3(256), 0, s, (C128 *)st, n, (const C128 *)mats,
-                           mstride, fold_off);
-    else
-        hipLaunchKernelGGL(k_init_product<float>, grid, dim3(256), 0, s, (C64 *)st, n, (const C64 *)mats,
-                           mstride, fold_off);
+    hipLaunchKernelGGL((k_init_product<T, M>), grid, dim3(256), 0, s, (cx<T> *)st, n, (const cx<M> *)mats, mstride,
+                       fold_off);
+}
+
+hipError_t launch_init_product(int dbl, int mdbl, void *st, int32_t n, int64_t batch, const void *mats,
+                               int64_t mstride, const int64_t *fold_off, hipStream_t s) {
+    if (dbl) init_product<double, double>(st, n, batch, mats, mstride, fold_off, s);
+    else if (mdbl) init_product<float, double>(st, n, batch, mats, mstride, fold_off, s);
+    else init_product<float, float>(st, n, batch, mats, mstride, fold_off, s);
     DQ_LAUNCH_RET;
 }
 

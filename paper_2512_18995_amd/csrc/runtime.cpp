@@ -189,7 +189,8 @@ struct DevData {
 
 struct dq_plan_s {
     int n = 0;
-    int dbl = 0;
+    int dbl = 0;                        // states in complex128
+    int mdbl = 0;                       // gate matrices and tile-pass arithmetic in float64
     dq_options opt{};
     int64_t nparams = 0, ndata = 0;
     std::vector<DGate> gates;
@@ -706,11 +707,11 @@ int default_R(const dq_plan_s &p) {
     // defaults keep two resident waves per SIMD: interpreted passes hold 32
     // complex64 (16 complex128) amplitudes per lane; compiled passes, which
     // need no registers for dispatch, hold twice that
-    const int base = p.opt.jit ? (p.dbl ? 5 : 6) : (p.dbl ? 4 : 5);
+    const int base = p.opt.jit ? (p.mdbl ? 5 : 6) : (p.mdbl ? 4 : 5);
     int R = p.opt.tile_bits > 0 ? p.opt.tile_bits : base;
     // 64 amplitudes per lane only in compiled passes: the interpreted kernel
     // cannot keep that many in registers (its tile went to scratch memory)
-    if ((p.dbl || !p.opt.jit) && R > 5) R = 5;
+    if ((p.mdbl || !p.opt.jit) && R > 5) R = 5;
     if (R > p.n - 6) R = p.n - 6;
     return R < 0 ? 0 : R;
 }
@@ -721,7 +722,7 @@ dq_status build_plan(dq_plan_s &p) {
     const bool fused = p.opt.fusion != 0;
     p.R_fwd = fused ? default_R(p) : 0;
     // two states per tile in the adjoint: fewer register bits by default
-    const int abase = p.opt.jit ? (p.dbl ? 4 : 5) : (p.dbl ? 3 : 4);
+    const int abase = p.opt.jit ? (p.mdbl ? 4 : 5) : (p.mdbl ? 3 : 4);
     int ra = p.opt.adj_tile_bits > 0 ? p.opt.adj_tile_bits : std::min(p.R_fwd, abase);
     if (ra > p.n - 6) ra = p.n - 6;
     p.R_adj = fused && ra > 0 ? ra : 0;
@@ -839,13 +840,14 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
         if (has_matrix(o.kind) && (s0 < 0 || o.slot < s0)) s0 = o.slot;
     }
     if (s0 < 0) s0 = 0;
-    const char *T = p.dbl ? "double" : "float";
+    const char *T = p.mdbl ? "double" : "float";              // arithmetic
+    const char *SS = p.dbl ? "double" : "float";              // storage
     const int R = S.R, NR = 1 << R, NS = adj ? 2 : 1;
     // compiled per plan: the streaming choice follows one sample's working set
     const char *nt = std::ldexp((double)NS * (p.dbl ? 16 : 8), p.n) > kStreamBytes ? "true" : "false";
     // occupancy target (waves per SIMD): two while a lane holds up to 64
     // complex64 amplitudes of one state (32 of each of two in the adjoint)
-    const int rb = NR * (p.dbl ? 8 : 4);
+    const int rb = NR * (p.mdbl ? 8 : 4);
     const int W = adj ? (rb >= 256 ? 1 : (rb >= 64 ? 2 : 4)) : (rb >= 512 ? 1 : (rb >= 128 ? 2 : 3));
     char line[256];
     std::string b;
@@ -854,9 +856,9 @@ std::string pass_body(const dq_plan_s &p, const Step &S, bool adj, int64_t &s0) 
     if (adj) {
         snprintf(line, sizeof line,
                  "    extern __shared__ double acc[];\n"
-                 "    dq::jit_adj<%s, %d, %s>(a, acc, [&](auto &v, auto m, int lane, double *ac) {\n", T, R, nt);
+                 "    dq::jit_adj<%s, %d, %s, %s>(a, acc, [&](auto &v, auto m, int lane, double *ac) {\n", T, R, nt, SS);
     } else {
-        snprintf(line, sizeof line, "    dq::jit_fwd<%s, %d, %s>(a, [&](auto &v, auto m, int lane) {\n", T, R, nt);
+        snprintf(line, sizeof line, "    dq::jit_fwd<%s, %d, %s, %s>(a, [&](auto &v, auto m, int lane) {\n", T, R, nt, SS);
     }
     b += line;
     const TOp *ops = p.ops.data() + S.op0;
@@ -971,6 +973,17 @@ void jit_generate(dq_plan_s &p) {
     gen(p.adj, true);
 }
 
+// every step of every program is a compiled tile pass (the float64
+// arithmetic of arith64 plans exists only in compiled passes)
+bool all_compiled(const dq_plan_s &p) {
+    for (const Program *pr : {&p.fwd_full, &p.fwd_fold, &p.adj}) {
+        if (pr == &p.fwd_fold && !p.has_fold) continue;
+        for (size_t k = 0; k < pr->steps.size(); ++k)
+            if (pr->steps[k].kind != ST_TILE || pr->jk.size() <= k || pr->jk[k] < 0) return false;
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------- qubit layout
 // Physical bits 0..2 (and, in large states, 3 and 4) are in every tile, so
 // the wires that sit there cost nothing to include in a pass.  When those
@@ -990,6 +1003,7 @@ dq_plan_s *plan_clone_base(const dq_plan_s &p) {
     auto *q = new dq_plan_s();
     q->n = p.n;
     q->dbl = p.dbl;
+    q->mdbl = p.mdbl;
     q->opt = p.opt;
     q->nparams = p.nparams;
     q->ndata = p.ndata;
@@ -1185,7 +1199,7 @@ WsLayout layout(const dq_plan_s &p, const dq_obs_s *o, int64_t batch, int per_sa
     const int64_t bm = per_sample ? batch : 1;
     size_t off = 0;
     L.mats = off;
-    off = align256(off + (size_t)bm * (size_t)std::max<int64_t>(p.block, 1) * amp);
+    off = align256(off + (size_t)bm * (size_t)std::max<int64_t>(p.block, 1) * (p.mdbl ? 16 : 8));
     L.expv = off;
     if (o) off = align256(off + (size_t)batch * expval_blocks(p.n, batch) * std::max<size_t>(o->terms.size(), 1) * 16);
     L.zdp = off;
@@ -1256,7 +1270,7 @@ dq_status run_program(dq_plan_s &p, DevData &d, const Program &prog, void *st, v
             a.nt = std::ldexp((double)batch * (lam ? 2 : 1) * (p.dbl ? 16 : 8), p.n) > kStreamBytes ? 1 : 0;
             const size_t si = (size_t)(&S - prog.steps.data());
             if (!prog.jk.empty() && prog.jk[si] >= 0 && (size_t)prog.jk[si] < d.jfn.size()) {
-                a.mats = (const char *)mats + prog.js0[si] * (p.dbl ? 16 : 8);
+                a.mats = (const char *)mats + prog.js0[si] * (p.mdbl ? 16 : 8);
                 e = jit_launch(d.jfn[prog.jk[si]], p.jnames[prog.jk[si]], a, lam != nullptr, s);
             } else {
                 e = lam ? launch_tile_adj(p.dbl, a, s) : launch_tile_fwd(p.dbl, a, s);
@@ -1325,7 +1339,7 @@ dq_status apply_on_device(dq_plan_s &p, DevData &d, void *state, int64_t batch, 
     const int64_t bm = per_sample ? batch : 1;
     const int64_t mstride = per_sample ? p.block : 0;
     ProfScope pp(p, DQ_PROF_OTHER, 1, 0.0, s, timed);
-    hipError_t e = launch_prepare(p.dbl, d.gates, d.fixed, d.slots + prog.slot_lo, (int32_t)(prog.slot_hi - prog.slot_lo),
+    hipError_t e = launch_prepare(p.mdbl, d.gates, d.fixed, d.slots + prog.slot_lo, (int32_t)(prog.slot_hi - prog.slot_lo),
                                   params, params_bstride, data, data_bstride, mats, p.block, bm, s);
     if (e == hipSuccess)
         e = launch_prepare_blocks(p.dbl, d.gates, d.fixed, d.blocks + prog.blk_lo, (int32_t)(prog.blk_hi - prog.blk_lo),
@@ -1334,7 +1348,7 @@ dq_status apply_on_device(dq_plan_s &p, DevData &d, void *state, int64_t batch, 
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
     if (from_zero) {
         ProfScope pi(p, DQ_PROF_INIT, 1, state_bytes(p, batch), s, timed);
-        if (fold) e = launch_init_product(p.dbl, state, p.n, batch, mats, mstride, d.fold, s);
+        if (fold) e = launch_init_product(p.dbl, p.mdbl, state, p.n, batch, mats, mstride, d.fold, s);
         else e = launch_init_zero(p.dbl, state, p.n, batch, s);
         pi.done();
     }
@@ -1376,7 +1390,7 @@ dq_status adjoint_core(dq_plan_s &plan, DevData &d, const dq_obs_s &obs, const D
         if (e != hipSuccess) return fail(DQ_ERR_HIP, "copy: %s", hipGetErrorString(e));
     }
     ProfScope pp(plan, DQ_PROF_OTHER, 1, 0.0, s);
-    e = launch_prepare(plan.dbl, d.gates, d.fixed, d.slots + plan.adj.slot_lo,
+    e = launch_prepare(plan.mdbl, d.gates, d.fixed, d.slots + plan.adj.slot_lo,
                        (int32_t)(plan.adj.slot_hi - plan.adj.slot_lo), params, params_bstride, data, data_bstride,
                        mats, plan.block, bm, s);
     pp.done();
@@ -1416,6 +1430,7 @@ dq_status ensure_hess_plan(dq_plan_s &p, dq_plan_s **out) {
         std::unique_ptr<dq_plan_s> q(new dq_plan_s());
         q->n = p.n;
         q->dbl = p.dbl;
+        q->mdbl = p.mdbl;
         q->opt = p.opt;
         q->nparams = (int64_t)p.occ_param.size();
         q->ndata = p.ndata;
@@ -1433,6 +1448,8 @@ dq_status ensure_hess_plan(dq_plan_s &p, dq_plan_s **out) {
         if (st != DQ_OK) return st;
         if (q->opt.layout == 0) q.reset(search_layout(q.release()));
         if (q->opt.jit) jit_generate(*q);
+        if (q->opt.arith64 && !all_compiled(*q))
+            return fail(DQ_ERR_UNSUPPORTED, "arith64: a step of the derived plan is not a compiled tile pass");
         p.hess = std::move(q);
     }
     *out = p.hess.get();
@@ -1525,8 +1542,11 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     if (ngates > (1 << 24)) return fail(DQ_ERR_OUT_OF_RANGE, "too many gates (%lld)", (long long)ngates);
     if (nparams < 0 || ndata < 0) return fail(DQ_ERR_INVALID_ARG, "negative nparams / ndata");
     if (dtype != DQ_C64 && dtype != DQ_C128) return fail(DQ_ERR_UNSUPPORTED, "dtype %d", (int)dtype);
-    dq_options o{1, 0, 1, 0, 0, 0, 0, 0};
+    dq_options o{1, 0, 1, 0, 0, 0, 0, 0, 0};
     if (opt) o = *opt;
+    if (o.arith64 != 0 && o.arith64 != 1) return fail(DQ_ERR_INVALID_ARG, "arith64 must be 0 or 1 (got %d)", o.arith64);
+    if (o.arith64 && (dtype != DQ_C64 || !o.jit || !o.fusion || o.dense_fuse))
+        return fail(DQ_ERR_UNSUPPORTED, "arith64 needs a complex64 plan with jit = 1, fusion = 1 and dense_fuse = 0");
     if (o.low_bits < 0 || o.low_bits > 3) return fail(DQ_ERR_INVALID_ARG, "low_bits %d outside 0..3", o.low_bits);
     if (o.layout != 0 && o.layout != 1) return fail(DQ_ERR_INVALID_ARG, "layout must be 0 or 1 (got %d)", o.layout);
     if (o.adj_tile_bits < 0 || o.adj_tile_bits > (dtype == DQ_C128 ? 4 : 5))
@@ -1538,6 +1558,7 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     std::unique_ptr<dq_plan_s> p(new dq_plan_s());
     p->n = nqubits;
     p->dbl = dtype == DQ_C128;
+    p->mdbl = p->dbl || o.arith64;
     p->opt = o;
     p->nparams = nparams;
     p->ndata = ndata;
@@ -1678,6 +1699,8 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
     }
     if (o.layout == 0) p.reset(search_layout(p.release()));
     if (o.jit) jit_generate(*p);
+    if (o.arith64 && !all_compiled(*p))
+        return fail(DQ_ERR_UNSUPPORTED, "arith64: a step of this plan is not a compiled tile pass");
     *out = p.release();
     return ok();
 } DQ_CATCH
@@ -2311,9 +2334,9 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
         m->plans.push_back(plans[c]);
         m->obs.push_back(obs[c]);
     }
-    // common tile shape: that of the first fused plan
+    // common tile shape: that of the first fused plan the shared kernels can run
     for (dq_plan p : m->plans)
-        if (p->R_fwd > 0) {
+        if (p->R_fwd > 0 && !p->opt.arith64) {
             m->R_fwd = p->R_fwd;
             m->R_adj = p->R_adj;
             break;
@@ -2334,7 +2357,8 @@ dq_status dq_multi_create(dq_multi *out, const dq_plan *plans, const dq_obs *obs
         const Program &f = p->has_fold ? p->fwd_fold : p->fwd_full;
         // batched: pure tile programs of the common shape, for which the
         // multi-circuit kernels exist; the rest take the single-plan path
-        m->batched.push_back(p->R_fwd > 0 && p->R_fwd == m->R_fwd && p->R_adj == m->R_adj && tile_only(f, m->R_fwd) &&
+        m->batched.push_back(!p->opt.arith64 && p->R_fwd > 0 && p->R_fwd == m->R_fwd && p->R_adj == m->R_adj &&
+                             tile_only(f, m->R_fwd) &&
                              tile_only(p->adj, m->R_adj) && multi_fwd_has(m->dbl, m->R_fwd) &&
                              multi_adj_has(m->dbl, m->R_adj));
     }

@@ -129,6 +129,11 @@ template <typename T> __device__ __forceinline__ void st_stream(cpx<T> *p, cpx<T
     __builtin_nontemporal_store(x, (v2 *)p);
 }
 
+// Storage and arithmetic types of a tile may differ (complex64 states swept
+// with float64 arithmetic): amplitudes are widened on load and rounded once
+// on store.
+template <typename T, typename S> __device__ __forceinline__ cpx<T> as_t(cpx<S> a) { return cpx<T>{(T)a.x, (T)a.y}; }
+
 __device__ __forceinline__ float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -705,18 +710,18 @@ template <typename T, int R> constexpr int adj_waves() { return (1 << R) * sizeo
 
 // One forward tile: load 2^R amplitudes per lane, run the operations
 // (body(v): an op-list interpreter, or a pass compiled at plan time), store.
-template <typename T, int R, typename Body>
-__device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, const int32_t *rbits, bool nt,
+template <typename T, int R, typename S = T, typename Body>
+__device__ __forceinline__ void fwd_tile(cx<S> *st, int64_t base, int64_t lo, const int32_t *rbits, bool nt,
                                          Body &&body) {
     using V = cx<T>;
     constexpr int NR = 1 << R;
     V v[1][NR];
     {
-        V *tp = st + base;
+        cx<S> *tp = st + base;
         if (nt) {
-            DQ_SF(NR, { v[0][i] = ld_stream(tp + reg_off<R>(i, rbits) + lo); });
+            DQ_SF(NR, { v[0][i] = as_t<T>(ld_stream(tp + reg_off<R>(i, rbits) + lo)); });
         } else {
-            DQ_SF(NR, { v[0][i] = (tp + reg_off<R>(i, rbits))[lo]; });
+            DQ_SF(NR, { v[0][i] = as_t<T>((tp + reg_off<R>(i, rbits))[lo]); });
         }
     }
     body(v);
@@ -724,11 +729,11 @@ __device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, co
     // 2^R per-lane pointers alive across the operations
     asm volatile("" : "+s"(base));
     {
-        V *tp = st + base;
+        cx<S> *tp = st + base;
         if (nt) {
-            DQ_SF(NR, { st_stream(tp + reg_off<R>(i, rbits) + lo, v[0][i]); });
+            DQ_SF(NR, { st_stream(tp + reg_off<R>(i, rbits) + lo, as_t<S>(v[0][i])); });
         } else {
-            DQ_SF(NR, { (tp + reg_off<R>(i, rbits))[lo] = v[0][i]; });
+            DQ_SF(NR, { (tp + reg_off<R>(i, rbits))[lo] = as_t<S>(v[0][i]); });
         }
     }
 }
@@ -738,8 +743,8 @@ __device__ __forceinline__ void fwd_tile(cx<T> *st, int64_t base, int64_t lo, co
 // acc) runs the pass on (psi, lambda), adding gradient terms into per-lane
 // float64 accumulators in LDS, which are reduced over the wave into
 // partial_row[lslot_gslot[s]].
-template <typename T, int R, typename Body>
-__device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, int64_t lbase, int n,
+template <typename T, int R, typename S = T, typename Body>
+__device__ __forceinline__ void adj_unit(cx<S> *st, cx<S> *lam, int64_t sbase, int64_t lbase, int n,
                                          const int32_t *rbits, const int32_t *lbits, const int32_t *tbits, int nls,
                                          int64_t w, int64_t wps, double *partial_row, const int32_t *lslot_gslot,
                                          double *acc, int lane, bool nt, Body &&body) {
@@ -752,34 +757,34 @@ __device__ __forceinline__ void adj_unit(cx<T> *st, cx<T> *lam, int64_t sbase, i
     for (int64_t t = w; t < tps; t += wps) {
         int64_t base = tile_base<R>(t, tbits);   // wave-uniform
         {
-            V *pp = st + sbase + base;
-            V *qp = lam + lbase + base;
+            cx<S> *pp = st + sbase + base;
+            cx<S> *qp = lam + lbase + base;
             if (nt) {
                 DQ_SF(NR, {
-                    v[0][i] = ld_stream(pp + reg_off<R>(i, rbits) + lo);
-                    v[1][i] = ld_stream(qp + reg_off<R>(i, rbits) + lo);
+                    v[0][i] = as_t<T>(ld_stream(pp + reg_off<R>(i, rbits) + lo));
+                    v[1][i] = as_t<T>(ld_stream(qp + reg_off<R>(i, rbits) + lo));
                 });
             } else {
                 DQ_SF(NR, {
-                    v[0][i] = (pp + reg_off<R>(i, rbits))[lo];
-                    v[1][i] = (qp + reg_off<R>(i, rbits))[lo];
+                    v[0][i] = as_t<T>((pp + reg_off<R>(i, rbits))[lo]);
+                    v[1][i] = as_t<T>((qp + reg_off<R>(i, rbits))[lo]);
                 });
             }
         }
         body(v, acc);
         asm volatile("" : "+s"(base));
         {
-            V *pp = st + sbase + base;
-            V *qp = lam + lbase + base;
+            cx<S> *pp = st + sbase + base;
+            cx<S> *qp = lam + lbase + base;
             if (nt) {
                 DQ_SF(NR, {
-                    st_stream(pp + reg_off<R>(i, rbits) + lo, v[0][i]);
-                    st_stream(qp + reg_off<R>(i, rbits) + lo, v[1][i]);
+                    st_stream(pp + reg_off<R>(i, rbits) + lo, as_t<S>(v[0][i]));
+                    st_stream(qp + reg_off<R>(i, rbits) + lo, as_t<S>(v[1][i]));
                 });
             } else {
                 DQ_SF(NR, {
-                    (pp + reg_off<R>(i, rbits))[lo] = v[0][i];
-                    (qp + reg_off<R>(i, rbits))[lo] = v[1][i];
+                    (pp + reg_off<R>(i, rbits))[lo] = as_t<S>(v[0][i]);
+                    (qp + reg_off<R>(i, rbits))[lo] = as_t<S>(v[1][i]);
                 });
             }
         }
@@ -1008,7 +1013,7 @@ __device__ __forceinline__ T gen_s(const cx<T> (&v)[NR], const cx<T> (&l)[NR], i
 // sample in a grid-stride loop; the adjoint runs work unit blockIdx.x of
 // sample blockIdx.y (as the interpreted passes do).  a.mats points at the
 // pass's first matrix.
-template <typename T, int R, bool NT, typename Body>
+template <typename T, int R, bool NT, typename S = T, typename Body>
 __device__ __forceinline__ void jit_fwd(const TileArgs &a, Body &&body) {
     using V = cx<T>;
     const int lane = threadIdx.x;
@@ -1020,17 +1025,17 @@ __device__ __forceinline__ void jit_fwd(const TileArgs &a, Body &&body) {
         const int64_t b = tile >> tshift;
         const int64_t base = (b << a.n) + tile_base<R>(tile & tmask, a.tbits);
         const cptr<V> m = to_const((const V *)a.mats + b * a.mstride);
-        fwd_tile<T, R>((V *)a.st, base, lo, a.rbits, NT, [&](V (&v)[1][1 << R]) { body(v, m, lane); });
+        fwd_tile<T, R, S>((cx<S> *)a.st, base, lo, a.rbits, NT, [&](V (&v)[1][1 << R]) { body(v, m, lane); });
     }
 }
 
-template <typename T, int R, bool NT, typename Body>
+template <typename T, int R, bool NT, typename S = T, typename Body>
 __device__ __forceinline__ void jit_adj(const TileArgs &a, double *acc, Body &&body) {
     using V = cx<T>;
     const int64_t b = blockIdx.y;
     const int lane = threadIdx.x;
     const cptr<V> m = to_const((const V *)a.mats + b * a.mstride);
-    adj_unit<T, R>((V *)a.st, (V *)a.lam, b << a.n, b << a.n, a.n, a.rbits, a.lbits, a.tbits, a.nlslots, blockIdx.x,
+    adj_unit<T, R, S>((cx<S> *)a.st, (cx<S> *)a.lam, b << a.n, b << a.n, a.n, a.rbits, a.lbits, a.tbits, a.nlslots, blockIdx.x,
                    a.wps, a.partial + (b * a.wps + blockIdx.x) * (int64_t)a.ngrad, a.lslot_gslot, acc, lane, NT,
                    [&](V (&v)[2][1 << R], double *ac) { body(v, m, lane, ac); });
 }

@@ -31,7 +31,7 @@ class Plan:
 
     def __init__(self, circuit, dtype: str = "c64", fusion: bool = True, tile_bits: int = 0,
                  fold_init: bool = True, dense_fuse: int = 0, jit: bool = False, adj_tile_bits: int = 0,
-                 low_bits: int = 0, layout: str = "auto"):
+                 low_bits: int = 0, layout: str = "auto", arith64: bool = False):
         self.n = int(circuit.n)
         self.dtype = dtype
         self.nparams = int(circuit.n_params)
@@ -40,7 +40,7 @@ class Plan:
         arr, keep = _lib.gate_array(self.gates)
         opt = _lib.DqOptions(1 if fusion else 0, int(tile_bits), 1 if fold_init else 0, int(dense_fuse),
                              1 if jit else 0, int(adj_tile_bits), int(low_bits),
-                             {"auto": 0, "canonical": 1}[layout])
+                             {"auto": 0, "canonical": 1}[layout], 1 if arith64 else 0)
         self.jit = bool(jit)
         h = ctypes.c_void_p()
         check(lib().dq_plan_create(ctypes.byref(h), self.n, arr, len(self.gates), self.nparams, self.ndata,

@@ -441,3 +441,36 @@ def test_noalloc_apply_validates_on_the_host(L):
     assert lib.dq_apply_circuit_noalloc(h, fake, 256, fake, 1800, None, 0, 1, None) == 4
     assert "scratch" in lib.dq_last_error().decode()
     lib.dq_plan_destroy(h)
+
+
+def test_arith64_option_validation(L):
+    """Float64 arithmetic on complex64 states: only for compiled, fused
+    complex64 plans without dense blocks; its tiles hold one register bit
+    less than complex64 arithmetic (as complex128 tiles do)."""
+    gates = [G("ry", (q,), "param", q) for q in range(20)] + [G("cnot", (q, (q + 1) % 20)) for q in range(20)]
+
+    def opt(**kw):
+        o = L.DqOptions(1, 0, 1, 0, 1, 0, 0, 0, 1)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    for bad, code in ((dict(jit=0), 2), (dict(fusion=0), 2), (dict(dense_fuse=4), 2), (dict(arith64=2), 1)):
+        st, h = _create(L, 20, gates, 20, 0, opt=opt(**bad))
+        assert st == code, (bad, st, L.lib().dq_last_error())
+    st, h = _create(L, 20, gates, 20, 0, dtype=1, opt=opt())
+    assert st == 2
+    # dense unitaries of two or more wires run as per-gate sweeps: not in arith64 plans
+    U = np.eye(4, dtype=np.complex128)
+    st, h = _create(L, 20, gates + [G("unitary", (3, 11), matrix=U)], 20, 0, opt=opt())
+    assert st == 2 and "compiled tile pass" in L.lib().dq_last_error().decode()
+    st, h = _create(L, 20, gates, 20, 0, opt=opt())
+    assert st == 0, L.lib().dq_last_error()
+    s = L.DqPlanStats()
+    assert L.lib().dq_plan_get_stats(h, ctypes.byref(s)) == 0
+    assert (s.tile_bits, s.adj_tile_bits) == (5, 4)
+    L.lib().dq_plan_destroy(h)
+    st, h = _create(L, 20, gates, 20, 0, opt=opt(arith64=0))
+    assert L.lib().dq_plan_get_stats(h, ctypes.byref(s)) == 0
+    assert (s.tile_bits, s.adj_tile_bits) == (6, 5)
+    L.lib().dq_plan_destroy(h)

@@ -96,26 +96,30 @@ def test_config3_sampled_against_oracle(jit):
 def test_config5_32_qubits_properties():
     """32 qubits, 20 layers, 1280 parameters (the benchmark's workload):
     the complex64 state stays normalised, |E| is within the coefficient
-    bound, E and the whole gradient match the complex128 path, and the
+    bound, E and the whole gradient match the complex128 path (with float64
+    arithmetic on complex64 storage, the benchmark's plan, to the 1e-5
+    target; with float32 arithmetic to twice its measured error), and the
     complex128 gradient matches central differences of complex128
     expectations on two parameters."""
     w = W.config(5)
     n = w.circuit.n
     obs = dq.Observable(n, w.observables)
-    plan = _plan(w)
-    st = plan.state(1, DEV)
     p = t64(w.params)
-    dq.apply_circuit(plan, st, p, None, from_zero=True)
-    print("config 5: complex64 forward done", flush=True)
-    nrm = float(torch.linalg.vector_norm(st).item())
-    E = dq.expval(plan, obs, st).cpu().numpy()
-    g, _ = dq.adjoint_grad(plan, obs, st, p, None, t64(np.ones((1, 1))))
-    g = g.cpu().numpy()
-    del st
-    torch.cuda.empty_cache()
-    assert abs(nrm - 1.0) < 1e-4
-    assert abs(E[0, 0]) <= sum(abs(c) for c, _ in w.observables[0])
-    print("config 5: complex64 adjoint done", flush=True)
+    res = {}
+    for arith64 in (True, False):
+        plan = dq.Plan(w.circuit, "c64", jit=True, arith64=arith64)
+        st = plan.state(1, DEV)
+        dq.apply_circuit(plan, st, p, None, from_zero=True)
+        print("config 5: complex64 forward done (float%d arithmetic)" % (64 if arith64 else 32), flush=True)
+        nrm = float(torch.linalg.vector_norm(st).item())
+        E = dq.expval(plan, obs, st).cpu().numpy()
+        g, _ = dq.adjoint_grad(plan, obs, st, p, None, t64(np.ones((1, 1))))
+        res[arith64] = (E, g.cpu().numpy())
+        del st, plan
+        torch.cuda.empty_cache()
+        assert abs(nrm - 1.0) < 1e-4
+        assert abs(E[0, 0]) <= sum(abs(c) for c, _ in w.observables[0])
+    print("config 5: complex64 adjoints done", flush=True)
     p128 = _plan(w, "c128")
     st = p128.state(1, DEV)
     dq.apply_circuit(p128, st, p, None, from_zero=True)
@@ -123,16 +127,22 @@ def test_config5_32_qubits_properties():
     E2 = dq.expval(p128, obs, st).cpu().numpy()
     g2, _ = dq.adjoint_grad(p128, obs, st, p, None, t64(np.ones((1, 1))))
     g2 = g2.cpu().numpy()
-    # complex64 at 1920 gates: the expectation holds the 1e-5 target
+    # float64 arithmetic on complex64 storage (one rounding per amplitude
+    # per pass): expectation and gradient within the 1e-5 target (measured
+    # 1.4e-7 and 1.7e-7)
+    E, g = res[True]
+    rel_e = normwise(E[0], E2[0], RTOL["c64"], 0.0, "expval complex64 (float64 arithmetic) vs complex128")
+    rel_g = normwise(g, g2, RTOL["c64"], 0.0, "gradient complex64 (float64 arithmetic) vs complex128")
+    print("config 5, float64 arithmetic: relative error expval %.2e, gradient %.2e" % (rel_e, rel_g), flush=True)
+    # float32 arithmetic at 1920 gates: the expectation holds the target
     # (measured 9e-8); the gradient does not: its absolute error is about
     # 2e-7 at 20 layers for every register size from 24 to 32 qubits, while
     # ||g|| shrinks with the register (2.5e-2 at 24 qubits, 5.4e-3 at 32),
-    # so the normwise error grows to 4.2e-5 here (1.0e-5 at 24 qubits).
-    # The bound is twice the measured error; the complex128 path, checked
-    # against central differences below, carries the 1e-5 claim at this size
+    # so the normwise error grows to 4.2e-5 here; bound: twice that
+    E, g = res[False]
     rel_e = normwise(E[0], E2[0], RTOL["c64"], 0.0, "expval complex64 vs complex128")
     rel_g = normwise(g, g2, 8.5e-5, 0.0, "gradient complex64 vs complex128")
-    print("config 5: complex64 vs complex128 relative error: expval %.2e, gradient %.2e" % (rel_e, rel_g), flush=True)
+    print("config 5, float32 arithmetic: relative error expval %.2e, gradient %.2e" % (rel_e, rel_g), flush=True)
     print("config 5: complex128 adjoint done", flush=True)
     h = 1e-4
     for k in (0, w.circuit.n_params - 1):

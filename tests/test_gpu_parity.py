@@ -713,3 +713,31 @@ def test_qresnet_listing_circuit(dtype, residual):
     tol = 1e-6 if dtype == "c64" else 1e-12
     normwise(gp.cpu().numpy(), rp, RTOL[dtype], tol, "d/dparams")
     normwise(gd.cpu().numpy(), rd, RTOL[dtype], tol, "d/ddata")
+
+
+@pytest.mark.parametrize("n,batch,per_sample", [(7, 2, True), (12, 3, False)])
+def test_arith64_forward_and_adjoint(n, batch, per_sample):
+    """Complex64 states swept with float64 arithmetic (compiled passes):
+    states, expectations and gradients for parameters and data against the
+    oracle, every gate kind; the state error stays within the complex64
+    bound for one rounding per pass."""
+    rng = np.random.default_rng(640 + n)
+    ops = ("h", "x", "rx", "ry", "rz", "cnot", "cz", "swap", "cp", "rzz", "rxx", "u3", "cry", "crz", "unitary")
+    c = W.random_circuit(rng, n, 8 * n, ops=ops, with_data=True, max_unitary_k=1)
+    params, data = W.random_params(rng, c, batch, per_sample)
+    obs = [W.random_pauli_sum(rng, n, 4), W.tfim_open(n, 0.5)]
+    w = rng.standard_normal((batch, len(obs)))
+    plan = dq.Plan(c, "c64", jit=True, arith64=True)
+    st = plan.state(batch, DEV)
+    dq.apply_circuit(plan, st, t64(params), t64(data), from_zero=True)
+    got = st.cpu().numpy()
+    for b in range(batch):
+        assert_state(got[b], oracle.state(c, params, data, b), "c64", plan.stats()["fwd_tile_passes"] + 1,
+                     "sample %d" % b)
+    O = dq.Observable(n, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    normwise(E, oracle.forward(c, params, data, obs, batch, threads=8), RTOL["c64"], 1e-7, "expval")
+    gp, gd = dq.adjoint_grad(plan, O, st, t64(params), t64(data), t64(w))
+    rp, rd = oracle.grad_param_shift(c, params, data, obs, w, batch, threads=8)
+    normwise(gp.cpu().numpy(), rp, RTOL["c64"], 1e-6, "d/dparams")
+    normwise(gd.cpu().numpy(), rd, RTOL["c64"], 1e-6, "d/ddata")

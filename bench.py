@@ -780,9 +780,13 @@ def result_errors(args, wl, plan, obs, params, data, E, gp, dev):
 
     def stat(v, r):
         d = np.abs(v - r)
+        # entrywise relative error over the entries that are not negligible:
+        # a gradient entry that is zero by symmetry has no relative error
+        big = np.abs(r) >= 1e-3 * np.abs(r).max() if r.size else np.zeros(0, bool)
         return {"rel_norm": float(np.linalg.norm(v - r) / max(np.linalg.norm(r), 1e-300)),
                 "max_abs": float(d.max()), "ref_norm": float(np.linalg.norm(r)),
-                "max_rel_entry": float((d / np.maximum(np.abs(r), 1e-300)).max())}
+                "max_rel_entry": float((d[big] / np.abs(r[big])).max()) if big.any() else 0.0,
+                "rel_entry_over": "entries with |ref| >= 1e-3 max |ref|"}
 
     out = {"reference": ref_name, "expval": stat(E, E_ref)}
     if g is not None:

@@ -488,16 +488,30 @@ __global__ __launch_bounds__(256) void k_dense_f32(C64 *st, int n, int64_t group
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = (gridDim.x * (int64_t)blockDim.x) >> 6;
     const int gshift = n - K - 5;
-    float A[MB][KK];
+    // K = 5 keeps only [Re U | Im U] (32 x 64, one register per k-step) and
+    // moves the sign and the real/imaginary swap of the real form onto the
+    // amplitudes:  Re y = [Re U | Im U] [Re x; -Im x],
+    //              Im y = [Re U | Im U] [Im x;  Re x].
+    // Half the matrix registers of the full real form, the same products.
+    constexpr int MA = K == 5 ? 1 : MB;
+    float A[MA][KK];
     int64_t cur = -1;
     for (int64_t g = wave; g < groups; g += nwaves) {
         const int64_t b = g >> gshift;
         if (b != cur) {
             const cptr<C64> U = to_const(mats + b * mstride + off);
+            if constexpr (K == 5) {
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
+                for (int kk = 0; kk < KK; ++kk) {
+                    const int c = 2 * kk + kq;
+                    A[0][kk] = c < D ? U[nn * D + c].x : U[nn * D + c - D].y;
+                }
+            } else {
 #pragma unroll
-                for (int kk = 0; kk < KK; ++kk) A[mb][kk] = real_form<D, float>(U, 32 * mb + nn, 2 * kk + kq);
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int kk = 0; kk < KK; ++kk) A[mb][kk] = real_form<D, float>(U, 32 * mb + nn, 2 * kk + kq);
+            }
             cur = b;
         }
         int64_t col = ((g & ((int64_t(1) << gshift) - 1)) << 5) | nn;
@@ -510,11 +524,21 @@ __global__ __launch_bounds__(256) void k_dense_f32(C64 *st, int n, int64_t group
         f32x16 acc[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x16{};
+        if constexpr (K == 5) {
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            const float bv = kk < XR ? x[kk].x : x[kk - XR].y;
+            for (int kk = 0; kk < KK; ++kk) {
+                const float br = kk < XR ? x[kk].x : -x[kk - XR].y;
+                const float bi = kk < XR ? x[kk].y : x[kk - XR].x;
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[0][kk], br, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[0][kk], bi, acc[1], 0, 0, 0);
+            }
+        } else {
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[mb][kk], bv, acc[mb], 0, 0, 0);
+            for (int kk = 0; kk < KK; ++kk) {
+                const float bv = kk < XR ? x[kk].x : x[kk - XR].y;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[mb][kk], bv, acc[mb], 0, 0, 0);
+            }
         }
         if constexpr (MB == 2) {
 #pragma unroll

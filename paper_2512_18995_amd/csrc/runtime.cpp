@@ -710,8 +710,10 @@ int default_R(const dq_plan_s &p) {
     const int base = p.opt.jit ? (p.mdbl ? 5 : 6) : (p.mdbl ? 4 : 5);
     int R = p.opt.tile_bits > 0 ? p.opt.tile_bits : base;
     // 64 amplitudes per lane only in compiled passes: the interpreted kernel
-    // cannot keep that many in registers (its tile went to scratch memory)
+    // cannot keep that many in registers (its tile went to scratch memory);
+    // the same holds for 32 complex128 amplitudes per lane, interpreted
     if ((p.mdbl || !p.opt.jit) && R > 5) R = 5;
+    if (!p.opt.jit && p.dbl && R > 4) R = 4;
     if (R > p.n - 6) R = p.n - 6;
     return R < 0 ? 0 : R;
 }
@@ -724,6 +726,9 @@ dq_status build_plan(dq_plan_s &p) {
     // two states per tile in the adjoint: fewer register bits by default
     const int abase = p.opt.jit ? (p.mdbl ? 4 : 5) : (p.mdbl ? 3 : 4);
     int ra = p.opt.adj_tile_bits > 0 ? p.opt.adj_tile_bits : std::min(p.R_fwd, abase);
+    // interpreted adjoint kernels exist up to 16 complex64 / 8 complex128
+    // amplitudes per lane and state: wider ones kept their tiles in scratch
+    if (!p.opt.jit && ra > (p.dbl ? 3 : 4)) ra = p.dbl ? 3 : 4;
     if (ra > p.n - 6) ra = p.n - 6;
     p.R_adj = fused && ra > 0 ? ra : 0;
     // gradient slots: every differentiable gate occurrence, in gate order

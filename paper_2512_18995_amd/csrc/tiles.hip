@@ -192,10 +192,15 @@ hipError_t DQ_FN(tile_fwd)(const TileArgs &a, hipStream_t s) {
     case 2: tile_fwd_r<2>(a, s); break;
     case 3: tile_fwd_r<3>(a, s); break;
     case 4: tile_fwd_r<4>(a, s); break;
-    case 5: tile_fwd_r<5>(a, s); break;
-    // no 64-amplitude interpreted kernel: with that many amplitudes per lane
-    // and the run-time dispatch, the compiler kept the tile in scratch
-    // memory; such passes are always compiled
+    case 5:
+        if constexpr (sizeof(T) == 4) {
+            tile_fwd_r<5>(a, s);
+            break;
+        }
+        return hipErrorInvalidValue;
+    // no interpreted kernel for 64 complex64 (32 complex128) amplitudes per
+    // lane: with that many and the run-time dispatch, the compiler kept the
+    // tile in scratch memory; such passes are always compiled
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -225,13 +230,13 @@ hipError_t DQ_FN(tile_adj)(const TileArgs &a, hipStream_t s) {
     case 1: hipLaunchKernelGGL((k_tile_adj<T, 1>), g, dim3(64), lds, s, a); break;
     case 2: hipLaunchKernelGGL((k_tile_adj<T, 2>), g, dim3(64), lds, s, a); break;
     case 3: hipLaunchKernelGGL((k_tile_adj<T, 3>), g, dim3(64), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_tile_adj<T, 4>), g, dim3(64), lds, s, a); break;
-    case 5:
+    case 4:
         if constexpr (sizeof(T) == 4) {
-            hipLaunchKernelGGL((k_tile_adj<T, 5>), g, dim3(64), lds, s, a);
+            hipLaunchKernelGGL((k_tile_adj<T, 4>), g, dim3(64), lds, s, a);
             break;
         }
         return hipErrorInvalidValue;
+    // wider interpreted adjoint tiles kept their registers in scratch memory
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -243,10 +248,9 @@ int DQ_FN(tile_adj_capacity)(int R) {
     case 1: return resident_waves(k_tile_adj<T, 1>, lds, 8 + 1);
     case 2: return resident_waves(k_tile_adj<T, 2>, lds, 8 + 2);
     case 3: return resident_waves(k_tile_adj<T, 3>, lds, 8 + 3);
-    case 4: return resident_waves(k_tile_adj<T, 4>, lds, 8 + 4);
     default:
-        if constexpr (sizeof(T) == 4) return resident_waves(k_tile_adj<T, 5>, lds, 8 + 5);
-        return resident_waves(k_tile_adj<T, 4>, lds, 8 + 4);
+        if constexpr (sizeof(T) == 4) return resident_waves(k_tile_adj<T, 4>, lds, 8 + 4);
+        return resident_waves(k_tile_adj<T, 3>, lds, 8 + 3);
     }
 }
 

@@ -380,6 +380,41 @@ def test_benchmark_plans_have_no_interpreted_wide_tiles():
                 assert nops << R <= 2048, (circuit.n, d, R, nops)
 
 
+def test_streaming_kernels_keep_no_registers_in_scratch(L):
+    """The build records the compiler's resource report of every kernel and
+    fails if a kernel that streams the state (tiles, dense blocks, per-gate
+    sweeps, init, expectations) keeps registers in scratch memory; the
+    record holds every interpreted tile kernel the launchers can reach."""
+    import json
+    from paper_2512_18995_amd import build as B
+    path = os.path.join(os.path.dirname(L.LIB_PATH), "_build", "kernel_resources.json")
+    res = json.load(open(path))
+    bases = {}
+    for k, v in res.items():
+        bases.setdefault(B.demangled_base(k), []).append(v)
+        if B.demangled_base(k).startswith(B.NO_SCRATCH):
+            assert v["scratch"] == 0, (k, v)
+    # complex64 forward tiles 1..5, complex128 1..4; adjoint 1..4 and 1..3
+    assert len(bases["k_tile_fwd"]) == 9 and len(bases["k_tile_adj"]) == 7, \
+        (len(bases["k_tile_fwd"]), len(bases["k_tile_adj"]))
+    assert len(bases["k_dense_f32"]) == 2 and len(bases["k_dense_f64"]) == 2
+
+
+def test_interpreted_tiles_are_clamped_to_the_built_kernels():
+    """Requested tile widths beyond the interpreted kernels that exist are
+    clamped on the host: complex128 forward 4 register bits, adjoint 3;
+    complex64 forward 5, adjoint 4."""
+    import paper_2512_18995_amd as dq
+    import workloads as W
+    c = W.config(5, n=14, layers=2).circuit
+    s = dq.Plan(c, "c128", tile_bits=5, adj_tile_bits=4).stats()
+    assert (s["tile_bits"], s["adj_tile_bits"]) == (4, 3), s
+    s = dq.Plan(c, "c64", tile_bits=5, adj_tile_bits=4).stats()
+    assert (s["tile_bits"], s["adj_tile_bits"]) == (5, 4), s
+    s = dq.Plan(c, "c64", tile_bits=6, jit=True).stats()      # compiled: the wide tiles stay
+    assert (s["tile_bits"], s["adj_tile_bits"]) == (6, 5), s
+
+
 def test_multi_plan_runs_unbatched_shapes_on_the_single_plan_path():
     """Circuits whose common tile shape has no multi-circuit kernel (an
     8-qubit first circuit gives 2 register bits; compiled plans use 6) are

@@ -122,6 +122,19 @@ struct DGroup {
     uint64_t xmask;
     int32_t t0, t1;            // term range
 };
+// Terms whose X mask is one bit, taken in register tiles of 2048 amplitudes:
+// lane l = physical bits 0..5, register k = the five bits rb (ascending, all
+// >= 6); one read of the state serves every such term whose X bit is a tile
+// bit.  pos: the X bit's place in the tile (0..5 lane bit, 6 + r register
+// bit r).
+constexpr int XT_MAX = 12;     // terms per tile set
+struct XSet {
+    int32_t rb[5];
+    int32_t x0, x1;            // XTerm range (at most XT_MAX)
+};
+struct XTerm {
+    int32_t t, pos;
+};
 
 }  // namespace dq
 
@@ -248,11 +261,15 @@ hipError_t launch_probs(int dbl, const void *st, int64_t batch, const ProbArgs &
                         double *out, hipStream_t s);
 hipError_t launch_sample(const double *p, int64_t batch, int32_t nout, const double *u, int32_t shots, int64_t *out,
                          hipStream_t s);
+// Groups [0, ngroups) by the pair kernels (the X-free group 0 by k_zdiag
+// when dt0 < dt1); the one-bit-X terms of the nxs tile sets (host array xs,
+// term lists at device xt) by the tile kernels (complex64 only).
 hipError_t launch_expval(int dbl, const void *st, int32_t n, int64_t batch, const DGroup *groups, int32_t ngroups,
                          const DTerm *terms, int32_t nterms, int32_t nobs, double *partial, int32_t eb, double *out,
-                         int32_t dt0, int32_t dt1, double *dpart, hipStream_t s);
+                         int32_t dt0, int32_t dt1, double *dpart, const XSet *xs, int32_t nxs, const XTerm *xt,
+                         hipStream_t s);
 hipError_t launch_lambda(int dbl, const void *psi, void *lam, int32_t n, int64_t batch, const DGroup *groups,
                          int32_t ngroups, const DTerm *terms, const double *grad_out, int32_t nobs, int32_t dt0, int32_t dt1,
-                         hipStream_t s);
+                         const XSet *xs, int32_t nxs, const XTerm *xt, hipStream_t s);
 
 }  // namespace dq

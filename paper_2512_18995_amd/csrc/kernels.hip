@@ -1078,6 +1078,158 @@ __global__ void k_expval_final(const double *partial, int64_t batch, int eb, con
     out[i] = e;
 }
 
+// ---------------------------------------------------------------- one-bit X terms in tiles
+// A wave owns tiles of 2048 amplitudes: lane l holds physical bits 0..5,
+// register k the five bits S.rb, so tile t starts at t << 6 with zeros
+// inserted at S.rb and every load reads 512 contiguous bytes.  A term X_h
+// (times a Z string) pairs amplitudes inside the tile: across lanes when h
+// is a lane bit (one backwards permute per register), across registers when
+// h is one of S.rb.  The sign (-1)^{|j & z|} splits into the tile base
+// (uniform), the lane and the register parts.
+__device__ __forceinline__ int64_t xtile_base(int64_t t, const XSet &S) {
+    int64_t b = t << 6;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) b = insert_zero(b, S.rb[r]);
+    return b;
+}
+__device__ __forceinline__ int64_t xtile_reg(int k, const XSet &S) {
+    int64_t o = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+        if ((k >> r) & 1) o += int64_t(1) << S.rb[r];
+    return o;
+}
+// the register part of a Z mask: bit r set when z holds S.rb[r]
+__device__ __forceinline__ int xtile_zr(uint64_t z, const XSet &S) {
+    int m = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) m |= (int)((z >> S.rb[r]) & 1) << r;
+    return m;
+}
+__device__ __forceinline__ C64 bperm_c64(C64 a, int addr) {
+    return C64{__int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(a.x))),
+               __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(a.y)))};
+}
+
+// Partial sums S_t = sum_j (-1)^{|j & z_t|} conj(psi_{j^x}) psi_j of the
+// set's terms (as expval_chunk: over the pair members j whose X bit is 0,
+// doubled), one row per block: partial[b][block][t][2].  Per tile and term
+// the wave's sum goes to a per-wave accumulator in LDS.
+__global__ __launch_bounds__(256) void k_xtile_expval(const C64 *st, int n, XSet S, const XTerm *xts, const DTerm *terms,
+                                                      int nterms, double *partial, int eb) {
+    __shared__ double acc[4][2 * XT_MAX];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t b = blockIdx.y, N = int64_t(1) << n;
+    const C64 *p = st + b * N;
+    const int nx = S.x1 - S.x0;
+    if (lane < 2 * XT_MAX) acc[wv][lane] = 0.0;
+    const int64_t ntiles = N >> 11;
+    for (int64_t t = blockIdx.x * 4 + wv; t < ntiles; t += (int64_t)eb * 4) {
+        const int64_t base = xtile_base(t, S);
+        C64 v[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) v[k] = p[base + xtile_reg(k, S) + lane];
+        for (int i = 0; i < nx; ++i) {
+            const XTerm x = xts[S.x0 + i];
+            const uint64_t z = terms[x.t].zmask;
+            const int h = x.pos < 6 ? x.pos : S.rb[x.pos - 6];
+            const bool odd = (z >> h) & 1;
+            const int zr = xtile_zr(z, S);
+            const int s0 = (__popcll((uint64_t)base & z) & 1) ^ (__popcll((uint64_t)lane & z) & 1);
+            double sr = 0.0;
+            if (x.pos < 6) {
+                const int addr = (lane ^ (1 << x.pos)) << 2;
+                const bool mine = !((lane >> x.pos) & 1);
+#pragma unroll
+                for (int k = 0; k < 32; ++k) {
+                    const C64 o = bperm_c64(v[k], addr), a = v[k];
+                    const double c = odd ? (double)(o.x * a.y - o.y * a.x) : (double)(o.x * a.x + o.y * a.y);
+                    const bool neg = (s0 ^ __popc(k & zr)) & 1;
+                    sr += neg ? -c : c;
+                }
+                if (!mine) sr = 0.0;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 5; ++r) {
+                    if (x.pos != 6 + r) continue;
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) {
+                        if ((k >> r) & 1) continue;
+                        const C64 a = v[k], o = v[k | (1 << r)];
+                        const double c = odd ? (double)(o.x * a.y - o.y * a.x) : (double)(o.x * a.x + o.y * a.y);
+                        const bool neg = (s0 ^ __popc(k & zr)) & 1;
+                        sr += neg ? -c : c;
+                    }
+                }
+            }
+            sr = wave_sum(sr);
+            if (lane == 0) acc[wv][2 * i + (odd ? 1 : 0)] += sr;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nx) {
+        const int ti = xts[S.x0 + (threadIdx.x >> 1)].t;
+        partial[((b * eb + blockIdx.x) * (int64_t)nterms + ti) * 2 + (threadIdx.x & 1)] =
+            2.0 * ((acc[0][threadIdx.x] + acc[1][threadIdx.x]) + (acc[2][threadIdx.x] + acc[3][threadIdx.x]));
+    }
+}
+
+// lambda_j (+)= sum over the set's terms of gout[b, obs_t] w_t
+// (-1)^{|(j ^ x_t) & z_t|} psi_{j ^ x_t}; one tile per wave at a time.
+__global__ __launch_bounds__(256) void k_xtile_lambda(const C64 *psi, C64 *lam, int n, int64_t batch, XSet S,
+                                                      const XTerm *xts, const DTerm *terms, const double *gout, int nobs,
+                                                      bool add) {
+    const int lane = threadIdx.x & 63;
+    const int nx = S.x1 - S.x0;
+    const int64_t ntiles = batch << (n - 11);
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < ntiles; t += nw) {
+        const int64_t b = t >> (n - 11);
+        const int64_t base = (b << n) + xtile_base(t & ((int64_t(1) << (n - 11)) - 1), S);
+        C64 v[32], l[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            v[k] = psi[base + xtile_reg(k, S) + lane];
+            l[k] = add ? lam[base + xtile_reg(k, S) + lane] : C64{0.f, 0.f};
+        }
+        for (int i = 0; i < nx; ++i) {
+            const XTerm x = xts[S.x0 + i];
+            const DTerm tm = terms[x.t];
+            const double g = gout[b * nobs + tm.obs];
+            const float wr = (float)(g * tm.wr), wi = (float)(g * tm.wi);
+            const int h = x.pos < 6 ? x.pos : S.rb[x.pos - 6];
+            // sign of the partner j ^ x: (-1)^{|j & z|} times (-1)^{z_h}
+            const int s0 = (__popcll((uint64_t)base & tm.zmask) & 1) ^ (__popcll((uint64_t)lane & tm.zmask) & 1) ^
+                           (int)((tm.zmask >> h) & 1);
+            const int zr = xtile_zr(tm.zmask, S);
+            if (x.pos < 6) {
+                const int addr = (lane ^ (1 << x.pos)) << 2;
+#pragma unroll
+                for (int k = 0; k < 32; ++k) {
+                    const C64 o = bperm_c64(v[k], addr);
+                    const bool neg = (s0 ^ __popc(k & zr)) & 1;
+                    const float dr = neg ? -wr : wr, di = neg ? -wi : wi;
+                    l[k] = C64{l[k].x + (dr * o.x - di * o.y), l[k].y + (dr * o.y + di * o.x)};
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 5; ++r) {
+                    if (x.pos != 6 + r) continue;
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) {
+                        const C64 o = v[k ^ (1 << r)];
+                        const bool neg = (s0 ^ __popc(k & zr)) & 1;
+                        const float dr = neg ? -wr : wr, di = neg ? -wi : wi;
+                        l[k] = C64{l[k].x + (dr * o.x - di * o.y), l[k].y + (dr * o.y + di * o.x)};
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k) lam[base + xtile_reg(k, S) + lane] = l[k];
+    }
+}
+
 // lambda_j = sum_k gout[b, obs_k] * coef_k i^{nY_k} (-1)^{|(j^x_k) & z_k|} psi_{j ^ x_k}
 // (for the X-free group the terms collapse into one factor d(j) psi_j)
 template <typename T>
@@ -1576,7 +1728,12 @@ hipError_t launch_sample(const double *p, int64_t batch, int32_t nout, const dou
 
 hipError_t launch_expval(int dbl, const void *st, int32_t n, int64_t batch, const DGroup *groups, int32_t ngroups,
                          const DTerm *terms, int32_t nterms, int32_t nobs, double *partial, int32_t eb, double *out,
-                         int32_t dt0, int32_t dt1, double *dpart, hipStream_t s) {
+                         int32_t dt0, int32_t dt1, double *dpart, const XSet *xs, int32_t nxs, const XTerm *xt,
+                         hipStream_t s) {
+    if (nxs > 0 && (dbl || n < 11)) return hipErrorInvalidValue;
+    for (int k = 0; k < nxs; ++k)
+        hipLaunchKernelGGL(k_xtile_expval, dim3((unsigned)eb, (unsigned)batch), dim3(256), 0, s, (const C64 *)st, n, xs[k],
+                           xt, terms, nterms, partial, eb);
     // the X-free group (terms dt0..dt1, group 0) by k_zdiag when dt0 < dt1
     const bool zd = dt0 < dt1;
     const int deb = zd ? zdiag_blocks(n) : 0;
@@ -1609,9 +1766,19 @@ hipError_t launch_expval(int dbl, const void *st, int32_t n, int64_t batch, cons
 
 hipError_t launch_lambda(int dbl, const void *psi, void *lam, int32_t n, int64_t batch, const DGroup *groups,
                          int32_t ngroups, const DTerm *terms, const double *grad_out, int32_t nobs, int32_t dt0, int32_t dt1,
-                         hipStream_t s) {
+                         const XSet *xs, int32_t nxs, const XTerm *xt, hipStream_t s) {
+    if (nxs > 0 && (dbl || n < 11)) return hipErrorInvalidValue;
     const int64_t total = batch << n;
     const bool zd = dt0 < dt1;   // the X-free group (terms dt0..dt1, group 0) by k_zdiag
+    const int g0 = zd ? 1 : 0;
+    // the one-bit-X tile sets after the pair groups, each adding to lambda
+    auto tiles = [&](bool add) {
+        const int64_t waves = batch << (n - 11);
+        const unsigned g = (unsigned)((waves + 3) / 4 < 4096 ? (waves + 3) / 4 : 4096);
+        for (int k = 0; k < nxs; ++k)
+            hipLaunchKernelGGL(k_xtile_lambda, dim3(g), dim3(256), 0, s, (const C64 *)psi, (C64 *)lam, n, batch, xs[k], xt,
+                               terms, grad_out, nobs, add || k > 0);
+    };
     if (zd) {
         const int64_t q = (int64_t(1) << (n - 11)) / 4;
         dim3 g((unsigned)(q < 1 ? 1 : (q < 4096 ? q : 4096)), (unsigned)batch);
@@ -1621,15 +1788,20 @@ hipError_t launch_lambda(int dbl, const void *psi, void *lam, int32_t n, int64_t
         else
             hipLaunchKernelGGL((k_zdiag<float, true>), g, dim3(256), 0, s, (const C64 *)psi, (C64 *)lam, n, terms,
                                dt0, dt1, grad_out, nobs, (double *)nullptr);
-        if (ngroups <= 1) DQ_LAUNCH_RET;
+        if (ngroups <= 1) {
+            tiles(true);
+            DQ_LAUNCH_RET;
+        }
     }
-    const int g0 = zd ? 1 : 0;
-    if (dbl)
-        hipLaunchKernelGGL(k_lambda<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C128 *)psi,
-                           (C128 *)lam, n, total, groups, g0, ngroups, terms, grad_out, nobs, zd);
-    else
-        hipLaunchKernelGGL(k_lambda<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C64 *)psi,
-                           (C64 *)lam, n, total, groups, g0, ngroups, terms, grad_out, nobs, zd);
+    if (ngroups > g0 || (!zd && nxs == 0)) {
+        if (dbl)
+            hipLaunchKernelGGL(k_lambda<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C128 *)psi,
+                               (C128 *)lam, n, total, groups, g0, ngroups, terms, grad_out, nobs, zd);
+        else
+            hipLaunchKernelGGL(k_lambda<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, (const C64 *)psi,
+                               (C64 *)lam, n, total, groups, g0, ngroups, terms, grad_out, nobs, zd);
+    }
+    tiles(zd || ngroups > g0);
     DQ_LAUNCH_RET;
 }
 

@@ -246,7 +246,12 @@ struct dq_obs_s {
     int nobs = 0;
     std::vector<DGroup> groups;
     std::vector<DTerm> terms;
-    size_t og = 0, ot = 0;       // byte offsets of groups / terms in the device copy
+    // groups [0, npair) go through the pair kernels; the one-bit-X groups
+    // after them also through register tiles (complex64 states, n >= 11)
+    int npair = 0;
+    std::vector<XSet> xsets;
+    std::vector<XTerm> xterms;
+    size_t og = 0, ot = 0, ox = 0;   // byte offsets of groups / terms / tile terms in the device copy
     std::mutex mu;
     std::map<int, void *> dev;   // device -> [groups][terms]
 };
@@ -1143,6 +1148,68 @@ dq_status ensure_device(dq_plan_s &p, DevData **out) {
     return DQ_OK;
 }
 
+// One-bit-X groups (X_h times a Z string: the transverse-field terms of an
+// Ising Hamiltonian, for one) in register tiles of 2048 amplitudes, lanes on
+// physical bits 0..5: the first set takes registers on bits 6..10 and so
+// every such term with h < 11, later sets the remaining X bits five at a
+// time.  One read of the state per set instead of one per group.  The groups
+// move to the end of the group list, after the ones the pair kernels take.
+void plan_xtiles(dq_obs_s &o) {
+    o.npair = (int)o.groups.size();
+    if (o.n < 11) return;
+    std::vector<DGroup> pair, single;
+    for (const DGroup &g : o.groups) (__builtin_popcountll(g.xmask) == 1 ? single : pair).push_back(g);
+    if (single.empty()) return;
+    // register bits of each set; the set and tile place of every X bit
+    std::vector<std::vector<int>> regsets;
+    int set_of[64], pos_of[64];
+    bool low = false;
+    std::vector<int> high;
+    for (const DGroup &g : single) {
+        const int h = __builtin_ctzll(g.xmask);
+        if (h < 11) low = true;
+        else high.push_back(h);   // ascending: groups are sorted by X mask
+    }
+    if (low) {
+        regsets.push_back({6, 7, 8, 9, 10});
+        for (int h = 0; h < 11; ++h) {
+            set_of[h] = 0;
+            pos_of[h] = h;   // lane bit h, or register h - 6 at place 6 + (h - 6)
+        }
+    }
+    for (size_t i = 0; i < high.size(); i += 5) {
+        std::vector<int> rb(high.begin() + i, high.begin() + std::min(high.size(), i + 5));
+        for (int b = 6; (int)rb.size() < 5; ++b)   // pad with bits below 11 (n >= 11)
+            if (std::find(rb.begin(), rb.end(), b) == rb.end()) rb.push_back(b);
+        std::sort(rb.begin(), rb.end());
+        for (int r = 0; r < 5; ++r)
+            if (rb[r] >= 11) {
+                set_of[rb[r]] = (int)regsets.size();
+                pos_of[rb[r]] = 6 + r;
+            }
+        regsets.push_back(rb);
+    }
+    for (size_t k = 0; k < regsets.size(); ++k) {
+        std::vector<XTerm> ts;
+        for (const DGroup &g : single) {
+            const int h = __builtin_ctzll(g.xmask);
+            if (set_of[h] != (int)k) continue;
+            for (int t = g.t0; t < g.t1; ++t) ts.push_back(XTerm{t, pos_of[h]});
+        }
+        for (size_t i = 0; i < ts.size(); i += XT_MAX) {
+            XSet S{};
+            for (int r = 0; r < 5; ++r) S.rb[r] = regsets[k][r];
+            S.x0 = (int32_t)o.xterms.size();
+            for (size_t q = i; q < std::min(ts.size(), i + (size_t)XT_MAX); ++q) o.xterms.push_back(ts[q]);
+            S.x1 = (int32_t)o.xterms.size();
+            o.xsets.push_back(S);
+        }
+    }
+    o.groups = pair;
+    o.groups.insert(o.groups.end(), single.begin(), single.end());
+    o.npair = (int)pair.size();
+}
+
 dq_status ensure_obs(dq_obs_s &o, const DGroup **groups, const DTerm **terms) {
     int dev = 0;
     DQ_HIP(hipGetDevice(&dev));
@@ -1152,6 +1219,7 @@ dq_status ensure_obs(dq_obs_s &o, const DGroup **groups, const DTerm **terms) {
         std::vector<char> blob;
         o.og = put(blob, o.groups);
         o.ot = put(blob, o.terms);
+        o.ox = put(blob, o.xterms);
         void *d = nullptr;
         DQ_HIP(hipMalloc(&d, blob.size()));
         hipError_t e = hipMemcpy(d, blob.data(), blob.size(), hipMemcpyHostToDevice);
@@ -1165,6 +1233,25 @@ dq_status ensure_obs(dq_obs_s &o, const DGroup **groups, const DTerm **terms) {
     *groups = (const DGroup *)(b + o.og);
     *terms = (const DTerm *)(b + o.ot);
     return DQ_OK;
+}
+
+// The pair-kernel groups and tile sets of an expectation or adjoint seed on
+// a plan's state: the tile kernels take complex64 states only.
+struct ObsRun {
+    int32_t ngroups = 0, nxs = 0;
+    const XSet *xs = nullptr;
+    const XTerm *xt = nullptr;
+};
+ObsRun obs_run(const dq_plan_s &p, const dq_obs_s &o, const DTerm *terms) {
+    ObsRun r;
+    const bool tiles = !p.dbl && p.n >= 11 && !o.xsets.empty();
+    r.ngroups = tiles ? o.npair : (int32_t)o.groups.size();
+    if (tiles) {
+        r.nxs = (int32_t)o.xsets.size();
+        r.xs = o.xsets.data();
+        r.xt = (const XTerm *)((const char *)terms - o.ot + o.ox);
+    }
+    return r;
 }
 
 // ---------------------------------------------------------------- sizes
@@ -1402,9 +1489,10 @@ dq_status adjoint_core(dq_plan_s &plan, DevData &d, const dq_obs_s &obs, const D
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "prepare: %s", hipGetErrorString(e));
     int32_t dt0, dt1;
     zdiag_range(plan, obs, dt0, dt1);
+    const ObsRun orun = obs_run(plan, obs, t);
     ProfScope pl(plan, DQ_PROF_LAMBDA, 1, 2 * SB, s);
-    e = launch_lambda(plan.dbl, psi, lam, plan.n, batch, g, (int32_t)obs.groups.size(), t, grad_out, obs.nobs, dt0,
-                      dt1, s);
+    e = launch_lambda(plan.dbl, psi, lam, plan.n, batch, g, orun.ngroups, t, grad_out, obs.nobs, dt0, dt1, orun.xs,
+                      orun.nxs, orun.xt, s);
     pl.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "lambda: %s", hipGetErrorString(e));
     dq_status st = run_program(plan, d, plan.adj, psi, lam, batch, mats, mstride, partial, wps, s);
@@ -1865,6 +1953,7 @@ dq_status dq_obs_create(dq_obs *out, int32_t nqubits, const dq_pauli_term *terms
         const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
         o->terms.push_back(DTerm{all[i].z, all[i].c * re[ny], all[i].c * im[ny], all[i].obs, 0});
     }
+    plan_xtiles(*o);
     *out = o.release();
     return ok();
 } DQ_CATCH
@@ -1956,10 +2045,12 @@ dq_status dq_expval(dq_plan plan, dq_obs obs, const void *state, int64_t batch, 
     const int eb = (int)expval_blocks(plan->n, batch);
     int32_t dt0, dt1;
     if (!zdiag_range(*plan, *obs, dt0, dt1) || obs->nobs > ZD_MAXOBS) dt0 = dt1 = 0;
-    ProfScope pe(*plan, DQ_PROF_EXPVAL, 2, state_bytes(*plan, batch) * (double)obs->groups.size(), (hipStream_t)stream);
-    hipError_t e = launch_expval(plan->dbl, state, plan->n, batch, g, (int32_t)obs->groups.size(), t,
-                                 (int32_t)obs->terms.size(), obs->nobs, (double *)((char *)ws + L.expv), eb, out, dt0,
-                                 dt1, (double *)((char *)ws + L.zdp), (hipStream_t)stream);
+    const ObsRun orun = obs_run(*plan, *obs, t);
+    ProfScope pe(*plan, DQ_PROF_EXPVAL, 2, state_bytes(*plan, batch) * (double)(orun.ngroups + orun.nxs),
+                 (hipStream_t)stream);
+    hipError_t e = launch_expval(plan->dbl, state, plan->n, batch, g, orun.ngroups, t, (int32_t)obs->terms.size(),
+                                 obs->nobs, (double *)((char *)ws + L.expv), eb, out, dt0, dt1,
+                                 (double *)((char *)ws + L.zdp), orun.xs, orun.nxs, orun.xt, (hipStream_t)stream);
     pe.done();
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "expval: %s", hipGetErrorString(e));
     return ok();

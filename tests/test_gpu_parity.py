@@ -143,6 +143,57 @@ def test_diagonal_observables(dtype, n, batch, nobs):
     normwise(gp[:, idx], rp[:, idx], RTOL[dtype], tol, "d/dparams")
 
 
+def _one_x_sums(rng, n, nobs):
+    """Sums of terms with one X or Y (times Z on random other wires) on every
+    wire, one wire with more such terms than one tile launch takes, beside a
+    Z-only and a two-X term; physical bits 0..5 are lane bits of the tiles,
+    6..10 registers of the first set, higher ones later sets."""
+    def term(h, letter, zw):
+        s = ["I"] * n
+        s[h] = letter
+        for w in zw:
+            if int(w) != h:
+                s[int(w)] = "Z"
+        return "".join(s)
+    obs = [[] for _ in range(nobs)]
+    for o in range(nobs):
+        for h in range(n):
+            zw = rng.choice(n, size=int(rng.integers(0, 4)), replace=False)
+            obs[o].append((float(rng.standard_normal()), term(h, "XY"[int(rng.integers(2))], zw)))
+        crowd = int(rng.integers(n))
+        for k in range(14):
+            zw = rng.choice(n, size=int(rng.integers(1, 5)), replace=False)
+            obs[o].append((float(rng.standard_normal()), term(crowd, "XY"[k % 2], zw)))
+        obs[o].append((float(rng.standard_normal()), "ZZ" + "I" * (n - 2)))
+        obs[o].append((float(rng.standard_normal()), "XX" + "I" * (n - 2)))
+    return obs
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [11, 13, 17])
+def test_one_x_terms_expval_and_adjoint(dtype, n):
+    """Observables of one-X (or one-Y) terms times Z strings, as the
+    transverse field of an Ising Hamiltonian: complex64 plans take them in
+    register tiles (one state read per set of bits), complex128 plans by
+    pairs; expectations and adjoint gradients against the oracle."""
+    rng = np.random.default_rng(950 + n)
+    batch = 2
+    c = W.random_circuit(rng, n, 3 * n, ops=("h", "rx", "ry", "rz", "cnot", "cz"), with_data=False)
+    params, _ = W.random_params(rng, c, batch, True)
+    obs = _one_x_sums(rng, n, 2)
+    plan, st = gpu_forward(c, params, None, batch, dtype, True)
+    O = dq.Observable(n, obs)
+    E = dq.expval(plan, O, st).cpu().numpy()
+    for b in range(batch):
+        want = oracle.state(c, params, None, b)
+        normwise(E[b], oracle.expvals(n, want, obs), RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12,
+                 "expval sample %d" % b)
+    w = rng.standard_normal((batch, len(obs)))
+    gp, _ = dq.adjoint_grad(plan, O, st, t64(params), None, t64(w))
+    rp, _ = oracle.grad_param_shift(c, params, None, obs, w, batch, threads=8)
+    normwise(gp.cpu().numpy(), rp, RTOL[dtype], 1e-6 if dtype == "c64" else 1e-12, "d/dparams")
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_fold_init_matches_unfolded(dtype):
     rng = np.random.default_rng(7)

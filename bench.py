@@ -406,6 +406,17 @@ def bench_hessian(args):
            "checks": {"symmetry": float(np.max(np.abs(Hn - Hn.T)) / max(np.max(np.abs(Hn)), 1e-300)),
                       "frobenius": float(np.linalg.norm(Hn))},
            "roofline": None, "source_hash": kernel_source_hash()}
+    # effective bandwidth of the whole Hessian: every shifted circuit's tile
+    # passes move its state once (forward) or its state and lambda (adjoint)
+    stt = plan.stats()
+    sb = float(8 << n)
+    byts = 2 * P * (stt["fwd_tile_passes"] * 2 * sb + stt["adj_steps"] * 4 * sb)
+    out["roofline"] = {"bound": "hbm", "kernel": "whole Hessian (batched forward and adjoint of the shifted circuits)",
+                       "achieved": byts / dt / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": byts / dt / 1e9 / 8000.0,
+                       "traffic": None, "algorithmic_bytes_per_launch": byts, "avg_launch_ms": dt * 1e3,
+                       "note": "effective: the %d shifted %d-qubit states (%.2f GB) sit in the 256 MB last-level "
+                               "cache only in part; passes per circuit %d forward, %d adjoint"
+                               % (2 * P, n, 2 * P * sb / 1e9, stt["fwd_tile_passes"], stt["adj_steps"])}
     print(json.dumps(out), flush=True)
 
 

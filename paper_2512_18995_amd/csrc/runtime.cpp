@@ -211,6 +211,11 @@ struct dq_plan_s {
     int64_t folded_gates = 0;
     int R_fwd = 0, R_adj = 0;
     int32_t ngrad = 0;
+    // the adjoint's gate order and gradient slots, and the sizes of what its
+    // planner appends to (slots, ops, lsg, factors, blocks, block), so that
+    // it can be planned again
+    std::vector<int> adj_rev, adj_gslot;
+    std::vector<size_t> adj_mark;
     std::vector<int64_t> poff, doff;
     std::vector<int32_t> pg, dg;
     std::vector<double> pf, df;
@@ -723,6 +728,51 @@ int default_R(const dq_plan_s &p) {
     return R < 0 ? 0 : R;
 }
 
+// (Re)plan the adjoint program, at most `cap` operations per tile pass when
+// cap > 0; returns its number of steps.
+size_t plan_adjoint(dq_plan_s &p, int cap) {
+    const auto &m = p.adj_mark;
+    p.slots.resize(m[0]);
+    p.ops.resize(m[1]);
+    p.lsg.resize(m[2]);
+    p.factors.resize(m[3]);
+    p.blocks.resize(m[4]);
+    p.block = (int64_t)m[5];
+    p.adj = Program();
+    Planner pl(p, true, p.R_adj);
+    if (cap > 0) pl.max_ops = pl.max_ops > 0 ? std::min(pl.max_ops, cap) : cap;
+    pl.gslot_of = p.adj_gslot;
+    pl.plan(p.adj, p.adj_rev, false);
+    return p.adj.steps.size();
+}
+
+// Compiled adjoint passes: the greedy packing leaves some passes much fuller
+// than the rest (the 32-qubit ring workload, float64 arithmetic: one pass
+// per layer with 21 operations beside passes of 15, running 47-54 ms
+// against 25-29 ms; two waves per SIMD cannot hide its arithmetic behind its
+// memory traffic).  The operations per pass are capped at the smallest value
+// that needs no more passes than the fewest any cap down to half the fullest
+// pass reaches (that workload: 121 passes, at most 18 operations; adjoint
+// 3.93 -> 3.55 s per step).  Run once, on the plan's final layout.
+void balance_adjoint(dq_plan_s &p) {
+    if (!p.opt.jit || p.R_adj <= 0 || p.adj_mark.empty()) return;
+    size_t best = p.adj.steps.size();
+    int most = 0;
+    for (const Step &S : p.adj.steps)
+        if (S.kind == ST_TILE) most = std::max(most, (int)S.nops);
+    int cap_best = 0;
+    for (int cap = most - 1; cap >= std::max(2, most / 2); --cap) {
+        const size_t n = plan_adjoint(p, cap);
+        if (n <= best) {
+            best = n;
+            cap_best = cap;
+        } else if (n > best + std::max<size_t>(2, best / 20)) {
+            break;   // well past the point where passes start to multiply
+        }
+    }
+    plan_adjoint(p, cap_best);
+}
+
 dq_status build_plan(dq_plan_s &p) {
     const int G_all = (int)p.gates.size();
     const int G = G_all - (int)p.entry_gates;   // the circuit proper; entry gates follow it in the list
@@ -815,13 +865,12 @@ dq_status build_plan(dq_plan_s &p) {
             p.fwd_fold.slot_lo = lo;
         }
     }
-    // adjoint: the reversed gate list, daggers, no fusion of one-qubit gates
-    {
-        std::vector<int> rev(order.rbegin(), order.rend());
-        Planner pl(p, true, p.R_adj);
-        pl.gslot_of = gslot;
-        pl.plan(p.adj, rev, false);
-    }
+    // adjoint: the reversed gate list, daggers, no fusion of one-qubit gates;
+    // what it needs to be planned again is kept (balance_adjoint)
+    p.adj_rev.assign(order.rbegin(), order.rend());
+    p.adj_gslot = gslot;
+    p.adj_mark = {p.slots.size(), p.ops.size(), p.lsg.size(), p.factors.size(), p.blocks.size(), (size_t)p.block};
+    plan_adjoint(p, 0);
     return DQ_OK;
 }
 
@@ -1540,6 +1589,7 @@ dq_status ensure_hess_plan(dq_plan_s &p, dq_plan_s **out) {
         dq_status st = build_plan(*q);
         if (st != DQ_OK) return st;
         if (q->opt.layout == 0) q.reset(search_layout(q.release()));
+        balance_adjoint(*q);
         if (q->opt.jit) jit_generate(*q);
         if (q->opt.arith64 && !all_compiled(*q))
             return fail(DQ_ERR_UNSUPPORTED, "arith64: a step of the derived plan is not a compiled tile pass");
@@ -1791,6 +1841,7 @@ dq_status dq_plan_create(dq_plan *out, int32_t nqubits, const dq_gate *gates, in
         return st;
     }
     if (o.layout == 0) p.reset(search_layout(p.release()));
+    balance_adjoint(*p);
     if (o.jit) jit_generate(*p);
     if (o.arith64 && !all_compiled(*p))
         return fail(DQ_ERR_UNSUPPORTED, "arith64: a step of this plan is not a compiled tile pass");

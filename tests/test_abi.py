@@ -415,6 +415,25 @@ def test_interpreted_tiles_are_clamped_to_the_built_kernels():
     assert (s["tile_bits"], s["adj_tile_bits"]) == (6, 5), s
 
 
+def test_adjoint_passes_balanced_for_float64_arithmetic():
+    """Compiled float64-arithmetic plans cap the operations per adjoint pass
+    at the smallest value that adds no pass: the 32-qubit ring workload keeps
+    121 adjoint passes with at most 18 operations each (greedy packing gave
+    one pass per layer 21); float32 arithmetic keeps the greedy packing."""
+    import paper_2512_18995_amd as dq
+    import workloads as W
+    c = W.config(5).circuit
+
+    def adj_ops(plan):
+        return [len(l.split(" ops=")[1].split(";")) for l in plan.describe().splitlines()
+                if l.startswith("adj") and " tile " in l]
+    a64 = dq.Plan(c, "c64", jit=True, arith64=True)
+    ops = adj_ops(a64)
+    assert len(ops) == 121 and max(ops) == 18, (len(ops), max(ops))
+    ops = adj_ops(dq.Plan(c, "c64", jit=True))
+    assert len(ops) == 100 and max(ops) == 26, (len(ops), max(ops))
+
+
 def test_multi_plan_runs_unbatched_shapes_on_the_single_plan_path():
     """Circuits whose common tile shape has no multi-circuit kernel (an
     8-qubit first circuit gives 2 register bits; compiled plans use 6) are

@@ -219,8 +219,9 @@ hipError_t launch_prepare_multi(int dbl, const MPrep *ents, int32_t nent, int32_
 hipError_t launch_init_multi(int dbl, void *st, const void *ws, const MInit *ents, int32_t nent, int32_t max_n,
                              hipStream_t s);
 // units: sum of the entries' eb; writes out[out_off + o] for every circuit
+// max_group: the most terms any X-mask group of the batched circuits holds
 hipError_t launch_expval_multi(int dbl, const void *st, void *ws, const MExp *ents, int32_t nent, int64_t units,
-                               double *out, hipStream_t s);
+                               int32_t max_group, double *out, hipStream_t s);
 // total: sum of the circuits' amplitudes (amp_begin ranges)
 hipError_t launch_lambda_multi(int dbl, const void *st, void *ws, const MExp *ents, int32_t nent, int64_t total,
                                const double *gout, hipStream_t s);

@@ -835,21 +835,21 @@ __global__ void k_hess_accum(const double *G, int64_t K, int64_t c0, int64_t mc,
 constexpr int EXP_TM = 32;
 
 // Partial sums S_t = sum_j (-1)^{|j & z_t|} conj(psi_{j^x}) psi_j over this
-// block's share of the amplitudes, for up to EXP_TM terms of one X-mask
-// group.  DIAG (x = 0): the product is |psi_j|^2, real.  Otherwise the
+// block's share of the amplitudes, for up to TM (<= EXP_TM) terms of one
+// X-mask group.  DIAG (x = 0): the product is |psi_j|^2, real.  Otherwise the
 // indices pair up as (j, j^x) with bit h (the highest of x) clear in j: the
 // summand at j^x is the conjugate of the one at j times
 // sigma = (-1)^{|x & z_t|}, so a pair adds 2 s_j Re(c) when sigma = +1 and
 // 2 i s_j Im(c) when sigma = -1 (c = conj(psi_{j^x}) psi_j), and each
 // amplitude is loaded once per group.
-template <typename T, bool DIAG>
+template <typename T, bool DIAG, int TM = EXP_TM>
 __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t x, cptr<DTerm> terms, int c0,
                                              int nt, double *row, int eb, double (*red)[2 * EXP_TM], int64_t blk) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint64_t z[EXP_TM];
-    double ar[EXP_TM], ai[EXP_TM];
+    uint64_t z[TM];
+    double ar[TM], ai[TM];
 #pragma unroll
-    for (int t = 0; t < EXP_TM; ++t) {
+    for (int t = 0; t < TM; ++t) {
         z[t] = t < nt ? terms[c0 + t].zmask : 0;
         ar[t] = 0.0;
         ai[t] = 0.0;
@@ -859,7 +859,7 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
             const cx<T> a = p[j];
             const double pr = (double)(a.x * a.x + a.y * a.y);
 #pragma unroll
-            for (int t = 0; t < EXP_TM; ++t) {
+            for (int t = 0; t < TM; ++t) {
                 if (t < nt) {
                     const bool neg = __popcll((uint64_t)j & z[t]) & 1;
                     ar[t] += neg ? -pr : pr;
@@ -869,9 +869,9 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
     } else {
         const int h = 63 - __clzll((long long)x);   // x != 0
         const int64_t lo = (int64_t(1) << h) - 1;
-        bool odd[EXP_TM];
+        bool odd[TM];
 #pragma unroll
-        for (int t = 0; t < EXP_TM; ++t) odd[t] = t < nt && (__popcll(x & z[t]) & 1);
+        for (int t = 0; t < TM; ++t) odd[t] = t < nt && (__popcll(x & z[t]) & 1);
         for (int64_t k = blk * blockDim.x + threadIdx.x; k < (N >> 1); k += (int64_t)eb * blockDim.x) {
             const int64_t j = ((k & ~lo) << 1) | (k & lo);
             const cx<T> a = p[j];
@@ -879,7 +879,7 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
             const double pr = (double)(o.x * a.x + o.y * a.y);
             const double pi = (double)(o.x * a.y - o.y * a.x);
 #pragma unroll
-            for (int t = 0; t < EXP_TM; ++t) {
+            for (int t = 0; t < TM; ++t) {
                 if (t < nt) {
                     const bool neg = __popcll((uint64_t)j & z[t]) & 1;
                     if (odd[t]) ai[t] += neg ? -pi : pi;
@@ -889,7 +889,7 @@ __device__ __forceinline__ void expval_chunk(const cx<T> *p, int64_t N, uint64_t
         }
     }
 #pragma unroll
-    for (int t = 0; t < EXP_TM; ++t) {
+    for (int t = 0; t < TM; ++t) {
         if (t < nt) {
             const double xr = DIAG ? wave_sum(ar[t]) : 2.0 * wave_sum(ar[t]);
             const double xi = DIAG ? 0.0 : 2.0 * wave_sum(ai[t]);
@@ -942,8 +942,12 @@ __device__ __forceinline__ int find_unit(const E *ents, int nent, int64_t u) {
 
 // Uneven batches: the expectation partial sums of every circuit in one
 // launch, block u doing chunk u - unit_begin of its circuit's eb chunks,
-// every X-mask group of the circuit (as k_expval_part).
-template <typename T>
+// every X-mask group of the circuit (as k_expval_part), TM terms of a group
+// per sweep over the amplitudes.  TM = 4 serves observables whose groups
+// hold at most four terms (a product of random Pauli strings has one term
+// per X mask) with a quarter of the registers of TM = EXP_TM, so more waves
+// stay resident to hide the loads' latency.
+template <typename T, int TM>
 __global__ __launch_bounds__(256) void k_expval_multi(const cx<T> *st, char *ws, const MExp *ents, int nent) {
     __shared__ double red[4][2 * EXP_TM];
     const int e = find_unit(ents, nent, blockIdx.x);
@@ -957,32 +961,37 @@ __global__ __launch_bounds__(256) void k_expval_multi(const cx<T> *st, char *ws,
     for (int g = 0; g < E.ngroups; ++g) {
         const uint64_t x = gp[g].xmask;
         const int t0 = gp[g].t0, t1 = gp[g].t1;
-        for (int c0 = t0; c0 < t1; c0 += EXP_TM) {
-            const int nt = (t1 - c0) < EXP_TM ? (t1 - c0) : EXP_TM;
-            if (x == 0) expval_chunk<T, true>(p, N, x, tp, c0, nt, row, E.eb, red, blk);
-            else expval_chunk<T, false>(p, N, x, tp, c0, nt, row, E.eb, red, blk);
+        for (int c0 = t0; c0 < t1; c0 += TM) {
+            const int nt = (t1 - c0) < TM ? (t1 - c0) : TM;
+            if (x == 0) expval_chunk<T, true, TM>(p, N, x, tp, c0, nt, row, E.eb, red, blk);
+            else expval_chunk<T, false, TM>(p, N, x, tp, c0, nt, row, E.eb, red, blk);
         }
     }
 }
 
-// out[out_off + o] = sum over the terms of observable o of Re(w_t S_t), the
-// chunks summed in order (one block per circuit, a thread per observable)
-__global__ void k_expval_final_multi(const char *ws, const MExp *ents, double *out) {
-    const MExp E = ents[blockIdx.x];
-    const double *part = (const double *)(ws + E.part_off);
-    for (int o = threadIdx.x; o < E.nobs; o += blockDim.x) {
+// out[out_off + o] = sum over the terms of observable o of Re(w_t S_t): one
+// wave per circuit, its lanes adding the chunks k = lane, lane + 64, ... in
+// order, then a fixed shuffle tree (deterministic).
+__global__ __launch_bounds__(64) void k_expval_final_multi(const char *ws, const MExp *ents, double *out) {
+    const cptr<MExp> ep = to_const(ents);
+    const int e = blockIdx.x, lane = threadIdx.x;
+    const double *part = (const double *)(ws + ep[e].part_off);
+    const cptr<DTerm> tp = to_const(ep[e].terms);
+    const int nterms = ep[e].nterms, nobs = ep[e].nobs, eb = ep[e].eb;
+    for (int o = 0; o < nobs; ++o) {
         double v = 0.0;
-        for (int t = 0; t < E.nterms; ++t) {
-            const DTerm tm = E.terms[t];
-            if (tm.obs != o) continue;
+        for (int t = 0; t < nterms; ++t) {
+            if (tp[t].obs != o) continue;
             double sr = 0.0, si = 0.0;
-            for (int k = 0; k < E.eb; ++k) {
-                sr += part[((int64_t)k * E.nterms + t) * 2];
-                si += part[((int64_t)k * E.nterms + t) * 2 + 1];
+            for (int k = lane; k < eb; k += 64) {
+                sr += part[((int64_t)k * nterms + t) * 2];
+                si += part[((int64_t)k * nterms + t) * 2 + 1];
             }
-            v += tm.wr * sr - tm.wi * si;
+            sr = wave_sum(sr);
+            si = wave_sum(si);
+            v += tp[t].wr * sr - tp[t].wi * si;
         }
-        out[E.out_off + o] = v;
+        if (lane == 0) out[ep[e].out_off + o] = v;
     }
 }
 
@@ -1272,39 +1281,49 @@ __global__ __launch_bounds__(256) void k_lambda(const cx<T> *psi, cx<T> *lam, in
 
 // Uneven batches: every circuit's adjoint seed in one launch; amplitude i of
 // the concatenated circuits belongs to the entry whose [amp_begin, amp_begin
-// + 2^n) holds it; weights at gout + out_off.
+// + 2^n) holds it; weights at gout + out_off.  Every circuit holds a multiple
+// of 64 amplitudes (n >= 6), so the 64 amplitudes of a wave belong to one
+// circuit: the wave looks up its entry, terms and weights once, with scalar
+// loads, instead of every lane searching the entries.
 template <typename T>
 __global__ __launch_bounds__(256) void k_lambda_multi(const cx<T> *st, char *ws, const MExp *ents, int nent,
                                                       int64_t total, const double *gout) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const cptr<MExp> ep = to_const(ents);
+    const int lane = threadIdx.x & 63;
+    const int64_t wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + 64 * wv; i0 < total; i0 += stride) {
         int lo = 0, hi = nent - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (ents[mid].amp_begin <= i) lo = mid;
+            if (ep[mid].amp_begin <= i0) lo = mid;
             else hi = mid - 1;
         }
-        const MExp &E = ents[lo];
-        const int64_t j = i - E.amp_begin;
-        const cx<T> *p = st + E.st_off;
-        const double *go = gout + E.out_off;
+        const int64_t i = i0 + lane;
+        if (i >= total) continue;
+        const int64_t j = i - ep[lo].amp_begin;
+        const cx<T> *p = st + ep[lo].st_off;
+        const cptr<DGroup> gp = to_const(ep[lo].groups);
+        const cptr<DTerm> tp = to_const(ep[lo].terms);
+        const cptr<double> go = to_const(gout + ep[lo].out_off);
+        const int ng = ep[lo].ngroups;
         double ar = 0.0, ai = 0.0;
-        for (int g = 0; g < E.ngroups; ++g) {
-            const uint64_t x = E.groups[g].xmask;
+        for (int g = 0; g < ng; ++g) {
+            const uint64_t x = gp[g].xmask;
             const int64_t jx = j ^ (int64_t)x;
             double dr = 0.0, di = 0.0;
-            for (int t = E.groups[g].t0; t < E.groups[g].t1; ++t) {
-                const DTerm tm = E.terms[t];
-                const double w = go[tm.obs];
-                const bool neg = __popcll((uint64_t)jx & tm.zmask) & 1;
-                dr += neg ? -w * tm.wr : w * tm.wr;
-                di += neg ? -w * tm.wi : w * tm.wi;
+            for (int t = gp[g].t0; t < gp[g].t1; ++t) {
+                const double w = go[tp[t].obs];
+                const double wr = tp[t].wr, wi = tp[t].wi;
+                const bool neg = __popcll((uint64_t)jx & tp[t].zmask) & 1;
+                dr += neg ? -w * wr : w * wr;
+                di += neg ? -w * wi : w * wi;
             }
             const cx<T> o = p[jx];
             ar += dr * (double)o.x - di * (double)o.y;
             ai += dr * (double)o.y + di * (double)o.x;
         }
-        ((cx<T> *)(ws + E.lam_off))[j] = cx<T>{(T)ar, (T)ai};
+        ((cx<T> *)(ws + ep[lo].lam_off))[j] = cx<T>{(T)ar, (T)ai};
     }
 }
 
@@ -1644,14 +1663,21 @@ hipError_t launch_init_multi(int dbl, void *st, const void *ws, const MInit *ent
 }
 
 hipError_t launch_expval_multi(int dbl, const void *st, void *ws, const MExp *ents, int32_t nent, int64_t units,
-                               double *out, hipStream_t s) {
+                               int32_t max_group, double *out, hipStream_t s) {
     if (nent <= 0) return hipSuccess;
-    if (dbl)
-        hipLaunchKernelGGL(k_expval_multi<double>, dim3((unsigned)units), dim3(256), 0, s, (const C128 *)st, (char *)ws,
-                           ents, nent);
+    const bool narrow = max_group <= 4;
+    if (dbl && narrow)
+        hipLaunchKernelGGL((k_expval_multi<double, 4>), dim3((unsigned)units), dim3(256), 0, s, (const C128 *)st,
+                           (char *)ws, ents, nent);
+    else if (dbl)
+        hipLaunchKernelGGL((k_expval_multi<double, EXP_TM>), dim3((unsigned)units), dim3(256), 0, s, (const C128 *)st,
+                           (char *)ws, ents, nent);
+    else if (narrow)
+        hipLaunchKernelGGL((k_expval_multi<float, 4>), dim3((unsigned)units), dim3(256), 0, s, (const C64 *)st,
+                           (char *)ws, ents, nent);
     else
-        hipLaunchKernelGGL(k_expval_multi<float>, dim3((unsigned)units), dim3(256), 0, s, (const C64 *)st, (char *)ws,
-                           ents, nent);
+        hipLaunchKernelGGL((k_expval_multi<float, EXP_TM>), dim3((unsigned)units), dim3(256), 0, s, (const C64 *)st,
+                           (char *)ws, ents, nent);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_expval_final_multi, dim3((unsigned)nent), dim3(64), 0, s, (const char *)ws, ents, out);

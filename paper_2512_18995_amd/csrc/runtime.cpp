@@ -2314,6 +2314,7 @@ struct dq_multi_s {
         MGrad *grad = nullptr;
         int32_t max_slots_fwd = 0, max_slots_adj = 0, max_n = 0;
         int64_t exp_units = 0, lam_total = 0, grad_total = 0;
+        int32_t exp_max_group = 0;   // the most terms of one X-mask group over the batched circuits
     };
     std::map<int, Dev> dev;
 };
@@ -2409,6 +2410,8 @@ dq_status ensure_multi(dq_multi_s &m, dq_multi_s::Dev **out) {
         const DTerm *t = nullptr;
         dq_status st = ensure_obs(*m.obs[c], &g, &t);
         if (st != DQ_OK) return st;
+        // the adjoint-seed kernel takes a wave's 64 amplitudes from one circuit
+        if (p->n < 6) return fail(DQ_ERR_INTERNAL, "multi-plan circuit %d: batched with %d qubits", c, p->n);
         MExp X{};
         X.st_off = m.st_off[c];
         X.lam_off = (int64_t)(wo + L.lam);
@@ -2423,6 +2426,7 @@ dq_status ensure_multi(dq_multi_s &m, dq_multi_s::Dev **out) {
         X.nterms = (int32_t)m.obs[c]->terms.size();
         X.nobs = m.obs[c]->nobs;
         X.eb = (int32_t)expval_blocks(p->n, 1);
+        for (const auto &gr_ : m.obs[c]->groups) D.exp_max_group = std::max(D.exp_max_group, gr_.t1 - gr_.t0);
         ex.push_back(X);
         D.exp_units += X.eb;
         D.lam_total += int64_t(1) << p->n;
@@ -2646,7 +2650,7 @@ dq_status dq_multi_expval(dq_multi m, const void *states, double *out, void *ws,
                             (char *)ws + m->ws_off[c], m->lay[c].total, stream)) != DQ_OK)
             return st;
     }
-    const hipError_t e = launch_expval_multi(m->dbl, states, ws, D->exp, (int32_t)m->bc.size(), D->exp_units, out,
+    const hipError_t e = launch_expval_multi(m->dbl, states, ws, D->exp, (int32_t)m->bc.size(), D->exp_units, D->exp_max_group, out,
                                              (hipStream_t)stream);
     if (e != hipSuccess) return fail(DQ_ERR_HIP, "multi expval: %s", hipGetErrorString(e));
     return ok();

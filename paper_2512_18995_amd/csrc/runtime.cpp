@@ -341,6 +341,13 @@ struct Planner {
         return hi <= R + 3;
     }
     bool diff(int g) const { return adjoint && p.gates[g].src != SRC_NONE && is_rotation(p.gates[g].op); }
+    // With float64 arithmetic in compiled passes a diagonal one-qubit gate
+    // does not fold into a non-diagonal slot, nor the reverse: the pass then
+    // applies RY as a real matrix and takes the RZs of its bits as one
+    // diagonal run (one complex product per amplitude for all of them)
+    // instead of a dense matrix per bit (32-qubit, 20-layer forward: 1588 ->
+    // 1496 ms).
+    bool diag_apart() const { return p.opt.jit && p.opt.arith64; }
 
     // Greedy in-order selection of the gates one tile pass can execute when
     // the free tile bits are S (grown up to R + 3 bits while scanning; bits
@@ -352,6 +359,7 @@ struct Planner {
         int lslots = 0;
         int ops = 0;                // operations after folding, as plan() will fold
         uint64_t last_1q = 0;       // bits whose last selected gate is a one-qubit gate
+        uint64_t diag_1q = 0;       // bits whose current one-qubit slot is diagonal
         int scount[64];             // per bit: gates folded into its current one-qubit slot
         auto popc = [](uint64_t x) { return __builtin_popcountll(x); };
         if (seed >= 0) {
@@ -374,7 +382,9 @@ struct Planner {
                 blocked |= Q;
                 continue;
             }
-            const bool folds = fusing && nq == 1 && ((last_1q >> q[0]) & 1) && scount[q[0]] < SLOT_MAXF;
+            const bool dg = nq == 1 && is_diag1(p.gates[g].op);
+            const bool folds = fusing && nq == 1 && ((last_1q >> q[0]) & 1) && scount[q[0]] < SLOT_MAXF &&
+                               (!diag_apart() || dg == (((diag_1q >> q[0]) & 1) != 0));
             if (max_ops && !folds && ops >= max_ops) break;
             S |= need;
             out.push_back((int)r);
@@ -383,6 +393,8 @@ struct Planner {
             if (nq == 1) {
                 scount[q[0]] = folds ? scount[q[0]] + 1 : 1;
                 last_1q |= 1ull << q[0];
+                if (dg && !folds) diag_1q |= 1ull << q[0];
+                else if (!dg) diag_1q &= ~(1ull << q[0]);
             } else {
                 last_1q &= ~Q;
             }
@@ -637,7 +649,10 @@ struct Planner {
                 op.lslot = -1;
                 if (G.nq == 1) {
                     const int prev = last_op[G.bits[0]];
-                    if (fuse_1q && prev >= st.op0 && (p.ops[prev].kind == TK_1Q || p.ops[prev].kind == TK_1QDIAG)) {
+                    // (as select() predicts: diagonal and non-diagonal gates
+                    // stay in separate slots where diag_apart())
+                    if (fuse_1q && prev >= st.op0 && (p.ops[prev].kind == TK_1Q || p.ops[prev].kind == TK_1QDIAG) &&
+                        (!diag_apart() || is_diag1(G.op) == (p.ops[prev].kind == TK_1QDIAG))) {
                         DSlot &sl = p.slots[op_slot[prev - st.op0]];
                         if (sl.nf < SLOT_MAXF) {   // fold into the previous one-qubit slot of this bit
                             sl.f[sl.nf++] = g;

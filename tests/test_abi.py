@@ -434,6 +434,29 @@ def test_adjoint_passes_balanced_for_float64_arithmetic():
     assert len(ops) == 100 and max(ops) == 26, (len(ops), max(ops))
 
 
+def test_float64_arithmetic_forward_keeps_rz_out_of_ry_and_every_pass_compiled():
+    """With float64 arithmetic the forward keeps diagonal one-qubit gates in
+    slots of their own (RZ runs apart from RY), and the pass selection counts
+    them as separate operations: random circuits of every gate kind still
+    compile every pass (arith64 plans refuse interpreted ones), and the
+    32-qubit ring workload keeps 101 forward passes with its 608 RY as real
+    matrices and its 608 RZ as diagonals."""
+    import paper_2512_18995_amd as dq
+    import workloads as W
+    ops = ("h", "x", "rx", "ry", "rz", "cnot", "cz", "swap", "cp", "rzz", "rxx", "u3", "cry", "crz", "unitary")
+    for n in (7, 12, 16):
+        for seed in range(4):
+            rng = np.random.default_rng(640 + n + 1000 * seed)
+            c = W.random_circuit(rng, n, 8 * n, ops=ops, with_data=True, max_unitary_k=1)
+            dq.Plan(c, "c64", jit=True, arith64=True)
+    s = dq.Plan(W.config(5).circuit, "c64", jit=True, arith64=True).stats()
+    assert s["fwd_tile_passes"] == 101, s
+    assert s["fwd_ops_reg"].get("1q_diag") == 608 and "1q" not in s["fwd_ops_reg"], s["fwd_ops_reg"]
+    assert s["fwd_ops_lane"].get("1q_real", 0) + s["fwd_ops_reg"].get("1q_real", 0) == 608, s
+    s32 = dq.Plan(W.config(5).circuit, "c64", jit=True).stats()
+    assert "1q_diag" not in s32["fwd_ops_reg"] and s32["fwd_ops_reg"].get("1q", 0) > 0, s32["fwd_ops_reg"]
+
+
 def test_multi_plan_runs_unbatched_shapes_on_the_single_plan_path():
     """Circuits whose common tile shape has no multi-circuit kernel (an
     8-qubit first circuit gives 2 register bits; compiled plans use 6) are

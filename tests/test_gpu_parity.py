@@ -411,20 +411,26 @@ def _uneven(count=7, nmin=10, nmax=14, lmin=2, lmax=4):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("variant", ["mixed", "first_circuit_8_qubits", "compiled_plans"])
+@pytest.mark.parametrize("variant", ["mixed", "grouped_observables", "first_circuit_8_qubits", "compiled_plans"])
 def test_multi_plan_matches_oracle(dtype, variant):
     """Circuits of uneven size in one multi-plan: every circuit's state,
     expectation and gradient equal the oracle's (and the single-plan path).
-    Variants whose tile shape has no multi-circuit kernel (a first circuit
-    of 8 qubits sets 2 register bits; compiled plans) run every circuit on
-    the single-plan path inside the same calls."""
+    Random Pauli sums hold one term per X mask (the expectation sweep's
+    4-term build); grouped_observables adds the transverse-field Ising sum,
+    whose n - 1 ZZ terms share the X mask 0 (the 32-term build).  Variants
+    whose tile shape has no multi-circuit kernel (a first circuit of 8
+    qubits sets 2 register bits; compiled plans) run every circuit on the
+    single-plan path inside the same calls."""
     mw = _uneven()
     if variant == "first_circuit_8_qubits":
         mw.items.insert(0, W.config(4, count=1, nmin=8, nmax=8, lmin=2, lmax=2).items[0])
+    if variant == "grouped_observables":
+        for it in mw.items:
+            it.observables = [W.tfim_open(it.circuit.n, 0.5)] + it.observables
     plans = [dq.Plan(it.circuit, dtype, jit=variant == "compiled_plans") for it in mw.items]
     obs = [dq.Observable(it.circuit.n, it.observables) for it in mw.items]
     M = dq.Multi(plans, obs)
-    if variant == "mixed":
+    if variant in ("mixed", "grouped_observables"):
         assert sum(M.batched) >= 2
     else:
         assert not any(M.batched)
@@ -437,13 +443,16 @@ def test_multi_plan_matches_oracle(dtype, variant):
     for c, it in enumerate(mw.items):
         want = oracle.state(it.circuit, it.params)
         assert_state(M.state_of(torch.as_tensor(got), c).numpy(), want, dtype, len(it.circuit.gates), "circuit %d" % c)
-        normwise([E[M.out_off[c]]], oracle.expvals(it.circuit.n, want, it.observables), RTOL[dtype],
+        no = len(it.observables)
+        normwise(E[M.out_off[c]:M.out_off[c] + no], oracle.expvals(it.circuit.n, want, it.observables), RTOL[dtype],
                  1e-6 if dtype == "c64" else 1e-12, "expval %d" % c)
     w = torch.as_tensor(np.random.default_rng(3).standard_normal(M.nout), device=DEV)
     g = M.adjoint_grad(st, params, w, ws).cpu().numpy()
+    wn = w.cpu().numpy()
     for c, it in enumerate(mw.items):
+        no = len(it.observables)
         rp, _ = oracle.grad_param_shift(it.circuit, it.params, None, it.observables,
-                                        np.array([[float(w[M.out_off[c]])]]), 1, threads=8)
+                                        wn[M.out_off[c]:M.out_off[c] + no][None, :], 1, threads=8)
         normwise(g[M.param_off[c]:M.param_off[c] + it.circuit.n_params], rp, RTOL[dtype],
                  1e-6 if dtype == "c64" else 1e-12, "gradient %d" % c)
 
